@@ -1,0 +1,245 @@
+/*
+ * tcm.h -- C ABI of the Tavis-Cummings density-matrix stepper for MI355X (gfx950).
+ *
+ * The library evolves the density matrix of n two-level atoms coupled to one
+ * cavity mode,  rho(t + dt) = U rho(t) U^dag  with  U = exp(-i H dt)  formed
+ * once (Miao & Ozhigov, arXiv 2403.06937, Sec. III.A, Eq. (6)), so every time
+ * step is two dense complex matrix-matrix products.  H is the Tavis-Cummings
+ * Hamiltonian of Sec. II, Eq. (4), with hbar = 1, a single bosonic cavity mode
+ * truncated at photon number c, per-atom frequencies w_a,i = 1 + delta_i and
+ * real couplings g_i.
+ *
+ * Basis order: photon-major Kronecker order |m>|l_1 ... l_n>, atom 1 the most
+ * significant bit, l_i = 1 for an excited atom; index s = m 2^n + sum_i l_i 2^(n-i),
+ * dimension N = (c + 1) 2^n.
+ *
+ * Conventions shared by every call
+ *   - Matrices are row-major with a leading dimension (ld >= N, in elements).
+ *   - Complex matrices are interleaved (re, im) pairs: tc_c128 (2 x double) or
+ *     tc_c64 (2 x float), the layout of torch.complex128 / torch.complex64.
+ *   - Pointers documented "device" must be device memory of the current HIP
+ *     device; "host" pointers are read during the call only.  The caller owns
+ *     all memory.  The library never allocates or frees caller memory; scratch
+ *     comes from a caller-provided workspace sized by the *_workspace_size
+ *     query of the same call.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it asynchronously; a call returns as soon as
+ *     its work is enqueued, unless documented otherwise.
+ *   - Every argument is validated before any device work is enqueued.  On
+ *     failure the return value is a TC_ERR_* code, no device work has been
+ *     enqueued for argument errors, outputs are unspecified for device errors,
+ *     and tc_last_error() returns a message for the calling thread (valid
+ *     until that thread's next library call).  No C++ exception crosses this
+ *     interface.
+ */
+#ifndef TCM_H
+#define TCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC_VERSION 100
+
+/* Status codes. */
+#define TC_OK                     0
+#define TC_ERR_INVALID_ARGUMENT   1
+#define TC_ERR_UNSUPPORTED        2
+#define TC_ERR_WORKSPACE          3
+#define TC_ERR_HIP                4
+#define TC_ERR_NONFINITE          5
+
+typedef struct { double re, im; } tc_c128;
+typedef struct { float re, im; } tc_c64;
+
+/* Storage type of rho at the interface. */
+#define TC_C64   1
+#define TC_C128  2
+
+/* Arithmetic of the per-step products. */
+#define TC_GEMM_F64          0   /* complex FP64 on FP64 MFMA                          */
+#define TC_GEMM_F32          1   /* complex FP32 on FP32 MFMA                          */
+#define TC_GEMM_SPLIT_BF16   2   /* each real operand split hi+lo in bfloat16; products
+                                    hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulate */
+
+/* Method of tc_expm. */
+#define TC_EXPM_SS_TAYLOR  0     /* shift, scale, Taylor (cos/sin) and squaring, FP64  */
+#define TC_EXPM_TAYLOR10   1     /* Sec. III.B, Eq. (10): sum_{k=0}^{10} (-i H dt)^k/k!,
+                                    no shift, no scaling                              */
+
+/* Frame in which the products run (the result is always the lab frame). */
+#define TC_FRAME_LAB       0
+#define TC_FRAME_ROTATING  1     /* rho~ = e^{+i w_c N t} rho e^{-i w_c N t}, where N is the
+                                    total excitation number; steps use U~ = I + D with
+                                    U~ = e^{+i w_c N dt} U, so the rounded operand is D  */
+
+/* Observable of tc_evolve_backward. */
+#define TC_OBS_EXCITED_TOTAL 0   /* L = sum_i <s_i^+ s_i^-> at the final step          */
+
+/* Model of Eq. (4). */
+typedef struct {
+  int32_t n_atoms;          /* n >= 1                                               */
+  int32_t photon_cutoff;    /* c >= 0: photon numbers 0..c, a^dag|c> = 0            */
+  double  omega_c;          /* cavity frequency                                     */
+  const double* omega_a;    /* host [n]: atomic frequencies 1 + delta_i             */
+  const double* g;          /* host [n]: real couplings g_i                         */
+} tc_model;
+
+/* ---------------------------------------------------------------- helpers */
+
+int         tc_version(void);
+const char* tc_last_error(void);
+
+/* N = (c + 1) 2^n.  TC_ERR_INVALID_ARGUMENT if n < 1, c < 0 or N > 2^31 / 16. */
+int tc_dim(int32_t n_atoms, int32_t photon_cutoff, int64_t* N);
+
+/* Host-only.  Gershgorin interval [lo, hi] containing the spectrum of H
+ * (Eq. (4)): centre H_ss, radius sum_i g_i sqrt(m+1) over the couplings that
+ * leave |m, l> (O(N n) work). */
+int tc_spectral_bounds(const tc_model* m, double* lam_lo, double* lam_hi);
+
+/* ----------------------------------------------------- a1: Hamiltonian */
+
+/* Writes the dense real symmetric Eq. (4) into H (device, N x N, row-major,
+ * leading dimension ldh >= N; columns N..ldh-1 are not touched):
+ *   H[s][s]  = w_c m + sum_i w_a,i l_i
+ *   H[t][s]  = H[s][t] = g_i sqrt(m + 1)  for s = (m, l) with l_i = 1, m < c and
+ *              t = (m + 1, l with l_i cleared)
+ *   every other entry exactly 0. */
+int tc_build_hamiltonian(const tc_model* m, double* H, int64_t ldh, void* stream);
+
+/* ------------------------------------------------------------ a2: expm */
+
+int tc_expm_workspace_size(int64_t N, int32_t method, size_t* bytes);
+
+/* U = exp(-i H dt) (Eq. (6) with hbar = 1) for real symmetric H (device, N x N,
+ * ldh), written to U (device, tc_c128 N x N, ldu).
+ * TC_EXPM_SS_TAYLOR: with mu = (lam_lo + lam_hi)/2 and the smallest s >= 0 such
+ * that (lam_hi - lam_lo)/2 |dt| 2^-s <= 1/2, B = (H - mu I) dt 2^-s, cos B and
+ * sin B from their Taylor series to degree 18 / 19 (remainder < 1e-17), then
+ * U = e^{-i mu dt} (cos B - i sin B)^(2^s), symmetrised.  lam_lo/hi must bound
+ * the spectrum (tc_spectral_bounds gives such bounds).
+ * TC_EXPM_TAYLOR10: Eq. (10), L = sum_{k=0}^{10} (-i H dt)^k / k!; lam_lo/hi
+ * are ignored.  The right factor of Eq. (11) is L^dag, which the stepper forms
+ * by conjugation.  ws: device workspace of tc_expm_workspace_size bytes. */
+int tc_expm(const double* H, int64_t N, int64_t ldh, double dt,
+            double lam_lo, double lam_hi, int32_t method,
+            tc_c128* U, int64_t ldu, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------- a3..a8: time stepping */
+
+typedef struct {
+  const tc_model* model;    /* host; its n, c define N                              */
+  int64_t N;                /* must equal (c + 1) 2^n                               */
+  const tc_c128* U;         /* device N x N propagator (tc_expm output), complex symmetric */
+  int64_t ldu;
+  void* rho;                /* device N x N, type opts.rho_dtype; in: rho(0), out: rho(steps) */
+  int64_t ldr;
+  double* pop_out;          /* device [steps/record_every + 1] or NULL: sum_i <s_i^+ s_i^-> */
+  double* photon_dist_out;  /* device [steps/record_every + 1][c + 1] or NULL: P(m)  */
+  void* checkpoints;        /* device [steps/checkpoint_every + 1][N][N] of rho_dtype, or NULL */
+} tc_instance;
+
+typedef struct {
+  int64_t steps;            /* >= 0                                                 */
+  double  dt;               /* time step of U (used by the rotating frame)          */
+  int32_t gemm_mode;        /* TC_GEMM_*                                            */
+  int32_t rho_dtype;        /* TC_C64 or TC_C128                                    */
+  int32_t frame;            /* TC_FRAME_*                                           */
+  int32_t renorm_every;     /* 0 = never; else Hermitise and divide by Re Tr rho in FP64
+                               after every renorm_every-th step                      */
+  int32_t record_every;     /* >= 1 when pop_out / photon_dist_out are given        */
+  int32_t checkpoint_every; /* 0 = none; else rho after every checkpoint_every-th step */
+  int32_t use_graph;        /* capture the per-chunk launches in a hipGraph         */
+  int32_t reserved;
+} tc_evolve_opts;
+
+int tc_evolve_workspace_size(const tc_instance* inst, int32_t count,
+                             const tc_evolve_opts* o, size_t* bytes);
+
+/* Steps each of the count instances o->steps times: rho <- U rho U^dag (Eq. (6);
+ * the paper's product order L (rho R) of Eq. (12) is the same product).
+ * Record r (r = 0 .. steps/record_every) holds the readout after r*record_every
+ * steps; record 0 is rho(0).  On return rho holds rho(steps) in the lab frame.
+ * count > 1 steps uneven instances together (all share o).  ws: device
+ * workspace of tc_evolve_workspace_size bytes.  Synchronises the stream only
+ * when a renormalisation finds a non-finite trace (then TC_ERR_NONFINITE). */
+int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------ a5/a7: observables */
+
+/* Readout of one density matrix (device, N x N, ldr, type rho_dtype).
+ * scalars (device [8]): Re Tr, Im Tr, purity sum |rho_ij|^2, max |rho - rho^dag|,
+ *   sum_i <s_i^+ s_i^->, <a^dag a>, <N_exc>, non-finite flag (1.0 if any entry
+ *   is NaN/Inf).  Diagonal readouts use Re rho_ss.
+ * atom_pop (device [n]) p_i, photon_dist (device [c + 1]) P(m),
+ * exc_dist (device [n + c + 1]) P_k: each may be NULL.
+ * ws: device workspace of tc_observables_workspace_size bytes (partial sums;
+ * the reductions run in a fixed order, so reruns are bitwise identical). */
+int tc_observables_workspace_size(int64_t N, size_t* bytes);
+int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype,
+                   int64_t N, int64_t ldr, double* scalars, double* atom_pop,
+                   double* photon_dist, double* exc_dist,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------- a9: differentiation */
+
+int tc_evolve_backward_workspace_size(const tc_model* m, int64_t N,
+                                      const tc_evolve_opts* o, size_t* bytes);
+
+/* Gradient of L = Tr(O rho(steps)), O = sum_i s_i^+ s_i^- (TC_OBS_EXCITED_TOTAL),
+ * with respect to g_i and delta_i (w_a,i = 1 + delta_i), for a run of tc_evolve
+ * with the same model, U and opts (frame lab, no renormalisation) whose
+ * checkpoints (device [steps/checkpoint_every + 1][N][N], rho_dtype) were
+ * recorded.  Adjoint: O_S = O, O_{s-1} = U^dag O_s U, M = sum_s rho_{s-1} U^dag O_s,
+ * G = L(A, M) the Frechet derivative of exp at A = -i H dt, and
+ * dL/dtheta = 2 Re Tr(dA/dtheta G).  H (device, N x N) is the Hamiltonian that
+ * built U.  loss_out (device [1] or NULL), grad_g / grad_delta (device [n]). */
+int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh,
+                       const tc_c128* U, int64_t ldu, int64_t N,
+                       const tc_evolve_opts* o, const void* checkpoints,
+                       int32_t observable, double* loss_out,
+                       double* grad_g, double* grad_delta,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------ kernel-level entry points */
+
+/* C = alpha op(A) op(B) + beta C for complex FP64 N x N matrices (device,
+ * tc_c128, row-major, leading dimensions lda/ldb/ldc >= N), op = identity,
+ * conjugate (op_* = 1) or transpose (op_* = 2) or conjugate transpose (3).
+ * ws: device workspace of tc_gemm_workspace_size bytes.  Runs the same MFMA
+ * kernel as the FP64 step. */
+int tc_gemm_workspace_size(int64_t M, int64_t N, int64_t K, int32_t mode, size_t* bytes);
+int tc_zgemm(int64_t M, int64_t N, int64_t K, tc_c128 alpha,
+             const tc_c128* A, int64_t lda, int32_t op_a,
+             const tc_c128* B, int64_t ldb, int32_t op_b,
+             tc_c128 beta, tc_c128* C, int64_t ldc, int32_t mode,
+             void* ws, size_t ws_bytes, void* stream);
+
+/* hi = RNE_bf16(x), lo = RNE_bf16(x - hi) for count binary32 values (device);
+ * hi, lo: device uint16 bit patterns.  The rounding used by TC_GEMM_SPLIT_BF16. */
+int tc_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, void* stream);
+
+/* ------------------------------------------------------ kernel timing */
+
+/* Kernel classes of tc_profile_read. */
+#define TC_KERNEL_GEMM_F64    0   /* FP64 MFMA products (step, expm)            */
+#define TC_KERNEL_GEMM_F32    1   /* FP32 MFMA products                         */
+#define TC_KERNEL_SPLIT_BF16  2   /* split-BF16 MFMA products                   */
+
+/* enable != 0: from now on every product-kernel launch is bracketed by two
+ * hipEvents recorded on the stream it is launched on (process-wide; previous
+ * records are dropped).  enable == 0 stops recording.  Host-only. */
+int tc_profile_enable(int32_t enable);
+/* Waits for the recorded events of one kernel class and returns the summed
+ * kernel time (ms) and the number of launches since tc_profile_enable(1). */
+int tc_profile_read(int32_t kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCM_H */

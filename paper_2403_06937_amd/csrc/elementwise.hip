@@ -1,0 +1,546 @@
+// HBM-bound and latency-bound kernels of libtcm: the Hamiltonian of Eq. (4),
+// helpers of the matrix exponential, frame changes, per-step diagonal readout,
+// FP64 renormalisation, full observables and the bfloat16 split.
+//
+// Reductions are deterministic: fixed per-thread strides, then a fixed LDS
+// tree inside one workgroup (no atomics), so reruns are bitwise identical.
+#include "kernels.h"
+
+namespace tcm {
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// Block-wide sum (all threads get the result).
+__device__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ double block_max(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ Eq. (4)
+__global__ void ham_fill_kernel(ModelArgs m, double* __restrict__ H, int64_t ldh) {
+  const int n = m.n;
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= m.N) return;
+  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y) {
+    const int64_t mr = row >> n, mc = col >> n;
+    const uint64_t lr = uint64_t(row) & mask, lc = uint64_t(col) & mask;
+    double v = 0.0;
+    if (row == col) {
+      v = m.omega_c * double(mr);
+      for (int i = 0; i < n; ++i)
+        if ((lr >> (n - 1 - i)) & 1) v += m.omega_a[i];
+    } else if (mr - mc == 1 || mc - mr == 1) {
+      // the state with fewer photons carries the one extra excited atom
+      const uint64_t llo = mr < mc ? lr : lc, lhi = mr < mc ? lc : lr;
+      const int64_t mhi = mr < mc ? mc : mr;
+      const uint64_t x = llo ^ lhi;
+      if (x != 0 && (x & (x - 1)) == 0 && (llo & x) != 0) {
+        const int bit = __ffsll((unsigned long long)x) - 1;
+        v = m.g[n - 1 - bit] * sqrt(double(mhi));
+      }
+    }
+    H[row * ldh + col] = v;
+  }
+}
+
+// ----------------------------------------------------- expm helpers
+__global__ void axpb_identity_kernel(const double* __restrict__ X, int64_t ldx, double a, double b,
+                                     double* __restrict__ out, int64_t ldo, int64_t N) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= N) return;
+  for (int64_t row = blockIdx.y; row < N; row += gridDim.y)
+    out[row * ldo + col] = a * X[row * ldx + col] + (row == col ? b : 0.0);
+}
+
+__global__ void assemble_cs_kernel(const double* __restrict__ Cm, const double* __restrict__ Sm,
+                                   int64_t ld, double pr, double pi, c128* __restrict__ U,
+                                   int64_t ldu, int64_t N) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= N) return;
+  for (int64_t row = blockIdx.y; row < N; row += gridDim.y) {
+    const double c = Cm[row * ld + col], sv = Sm[row * ld + col];
+    // (pr + i pi) (c - i s)
+    U[row * ldu + col] = c128{pr * c + pi * sv, pi * c - pr * sv};
+  }
+}
+
+__global__ void symmetrize_kernel(c128* __restrict__ U, int64_t ldu, int64_t N) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= N) return;
+  for (int64_t row = blockIdx.y; row < col; row += gridDim.y) {
+    const c128 a = U[row * ldu + col], b = U[col * ldu + row];
+    const c128 v{0.5 * (a.re + b.re), 0.5 * (a.im + b.im)};
+    U[row * ldu + col] = v;
+    U[col * ldu + row] = v;
+  }
+}
+
+// ----------------------------------------------------------- copies
+__global__ void c128_to_c64_kernel(const c128* __restrict__ s, int64_t lds, c64* __restrict__ d,
+                                   int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= cols) return;
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const c128 v = s[row * lds + col];
+    d[row * ldd + col] = c64{float(v.re), float(v.im)};
+  }
+}
+__global__ void c64_to_c128_kernel(const c64* __restrict__ s, int64_t lds, c128* __restrict__ d,
+                                   int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= cols) return;
+  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const c64 v = s[row * lds + col];
+    d[row * ldd + col] = c128{double(v.re), double(v.im)};
+  }
+}
+
+// ------------------------------------------------------ rotating frame
+__device__ __forceinline__ int exc_number(int64_t s, int n) {
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  return int(s >> n) + popc64(uint64_t(s) & mask);
+}
+
+template <typename E>
+__global__ void rotating_d_kernel(ModelArgs m, const c128* __restrict__ U, int64_t ldu, double dt,
+                                  E* __restrict__ D, int64_t ldd) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= m.N) return;
+  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y) {
+    double sn, cs;
+    sincos(m.omega_c * double(exc_number(row, m.n)) * dt, &sn, &cs);
+    const c128 u = U[row * ldu + col];
+    c128 v{cs * u.re - sn * u.im, cs * u.im + sn * u.re};
+    if (row == col) v.re -= 1.0;
+    typedef decltype(E().re) T;
+    D[row * ldd + col] = E{T(v.re), T(v.im)};
+  }
+}
+
+template <typename E>
+__global__ void frame_phase_kernel(ModelArgs m, E* __restrict__ rho, int64_t ld, double t) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= m.N) return;
+  const int kc = exc_number(col, m.n);
+  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y) {
+    const int kr = exc_number(row, m.n);
+    if (kr == kc) continue;
+    double sn, cs;
+    sincos(-m.omega_c * double(kr - kc) * t, &sn, &cs);
+    const E v = rho[row * ld + col];
+    const double re = double(v.re), im = double(v.im);
+    rho[row * ld + col] = E{decltype(v.re)(cs * re - sn * im), decltype(v.re)(cs * im + sn * re)};
+  }
+}
+
+// ------------------------------------------------------- per-step readout
+template <typename E>
+__global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t ld,
+                               double* __restrict__ pop, double* __restrict__ pdist) {
+  __shared__ double sh[TPB];
+  const int n = m.n;
+  const int64_t per = int64_t(1) << n;
+  const uint64_t mask = uint64_t(per - 1);
+  double tot = 0.0;
+  for (int mm = 0; mm <= m.c; ++mm) {
+    double part = 0.0, ex = 0.0;
+    for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
+      const double d = double(rho[s * ld + s].re);
+      part += d;
+      ex += double(popc64(uint64_t(s) & mask)) * d;
+    }
+    if (pdist) {
+      const double pm = block_sum(part, sh);
+      if (threadIdx.x == 0) pdist[mm] = pm;
+    }
+    tot += ex;
+  }
+  const double t = block_sum(tot, sh);
+  if (threadIdx.x == 0 && pop) *pop = t;
+}
+
+// ---------------------------------------------------- FP64 renormalisation
+template <typename E>
+__global__ void trace_kernel(const E* __restrict__ rho, int64_t ld, int64_t N, double* scratch) {
+  __shared__ double sh[TPB];
+  double part = 0.0;
+  for (int64_t s = threadIdx.x; s < N; s += TPB) part += double(rho[s * ld + s].re);
+  const double tr = block_sum(part, sh);
+  if (threadIdx.x == 0) {
+    scratch[0] = tr;
+    if (!(tr > 0.0) || !isfinite(tr)) scratch[1] = 1.0;
+  }
+}
+
+constexpr int RT = 32;  // tile edge of the pair kernels
+
+__device__ __forceinline__ void pair_index(int64_t b, int64_t& bi, int64_t& bj) {
+  // b -> (bi <= bj) over the upper triangle of tile pairs, row by row of bj:
+  // bj = floor((sqrt(8b+1)-1)/2), bi = b - bj(bj+1)/2
+  int64_t j = int64_t((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
+  while (j * (j + 1) / 2 > b) --j;
+  while ((j + 1) * (j + 2) / 2 <= b) ++j;
+  bj = j;
+  bi = b - j * (j + 1) / 2;
+}
+
+template <typename E>
+__global__ void renorm_kernel(E* __restrict__ rho, int64_t ld, int64_t N, const double* scratch) {
+  __shared__ double2 tA[RT][RT + 1];
+  __shared__ double2 tB[RT][RT + 1];
+  if (scratch[1] != 0.0) return;   // non-finite / non-positive trace: leave rho as is
+  const double inv = 1.0 / scratch[0];
+  int64_t bi, bj;
+  pair_index(blockIdx.x, bi, bj);
+  const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;   // 32 x 8
+  // load tile (bi, bj) and (bj, bi)
+  for (int r = ty; r < RT; r += TPB / RT) {
+    const int64_t i = bi * RT + r, j = bj * RT + tx;
+    if (i < N && j < N) { const E v = rho[i * ld + j]; tA[r][tx] = make_double2(v.re, v.im); }
+    const int64_t i2 = bj * RT + r, j2 = bi * RT + tx;
+    if (i2 < N && j2 < N) { const E v = rho[i2 * ld + j2]; tB[r][tx] = make_double2(v.re, v.im); }
+  }
+  __syncthreads();
+  // element (i, j) in tile A pairs with (j, i) = tB[tx][r]
+  for (int r = ty; r < RT; r += TPB / RT) {
+    const int64_t i = bi * RT + r, j = bj * RT + tx;
+    if (i < N && j < N) {
+      const double2 a = tA[r][tx], b = tB[tx][r];
+      double re = 0.5 * (a.x + b.x) * inv, im = 0.5 * (a.y - b.y) * inv;
+      if (i == j) im = 0.0;
+      typedef decltype(E().re) T;
+      rho[i * ld + j] = E{T(re), T(im)};
+      if (bi != bj) rho[j * ld + i] = E{T(re), T(-im)};
+    }
+  }
+}
+
+// ------------------------------------------------------------ observables
+// Pass 1: per tile pair (bi <= bj): purity partial, Hermiticity max,
+// non-finite count; diagonal tiles also copy their diagonal to diag[].
+template <typename E>
+__global__ void obs_pass1(const E* __restrict__ rho, int64_t ld, int64_t N,
+                          double* __restrict__ partials, double* __restrict__ diag) {
+  __shared__ double2 tA[RT][RT + 1];
+  __shared__ double2 tB[RT][RT + 1];
+  __shared__ double sh[TPB];
+  int64_t bi, bj;
+  pair_index(blockIdx.x, bi, bj);
+  const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
+  for (int r = ty; r < RT; r += TPB / RT) {
+    const int64_t i = bi * RT + r, j = bj * RT + tx;
+    tA[r][tx] = (i < N && j < N) ? make_double2(rho[i * ld + j].re, rho[i * ld + j].im) : make_double2(0, 0);
+    const int64_t i2 = bj * RT + r, j2 = bi * RT + tx;
+    tB[r][tx] = (i2 < N && j2 < N) ? make_double2(rho[i2 * ld + j2].re, rho[i2 * ld + j2].im) : make_double2(0, 0);
+  }
+  __syncthreads();
+  double pur = 0.0, herm = 0.0, bad = 0.0;
+  for (int r = ty; r < RT; r += TPB / RT) {
+    const double2 a = tA[r][tx], b = tB[tx][r];
+    const double2 b2 = tB[r][tx];
+    if (!isfinite(a.x) || !isfinite(a.y)) bad += 1.0;
+    pur += a.x * a.x + a.y * a.y;
+    if (bi != bj) {
+      if (!isfinite(b2.x) || !isfinite(b2.y)) bad += 1.0;
+      pur += b2.x * b2.x + b2.y * b2.y;
+    }
+    herm = fmax(herm, hypot(a.x - b.x, a.y + b.y));
+    if (bi == bj && r == tx) {
+      const int64_t i = bi * RT + r;
+      if (i < N) diag[i] = a.x;
+    }
+  }
+  const double P = block_sum(pur, sh);
+  const double Hm = block_max(herm, sh);
+  const double B = block_sum(bad, sh);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x + 0] = P;
+    partials[3 * blockIdx.x + 1] = Hm;
+    partials[3 * blockIdx.x + 2] = B;
+  }
+}
+
+__global__ void obs_pass2(ModelArgs m, const double* __restrict__ partials, int64_t npairs,
+                          const double* __restrict__ diag, const double* __restrict__ trace_im_src,
+                          double* __restrict__ scalars, double* __restrict__ atom_pop,
+                          double* __restrict__ photon_dist, double* __restrict__ exc_dist) {
+  __shared__ double sh[TPB];
+  const int n = m.n;
+  const int64_t N = m.N;
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  double pur = 0.0, herm = 0.0, bad = 0.0;
+  for (int64_t b = threadIdx.x; b < npairs; b += TPB) {
+    pur += partials[3 * b];
+    herm = fmax(herm, partials[3 * b + 1]);
+    bad += partials[3 * b + 2];
+  }
+  pur = block_sum(pur, sh);
+  herm = block_max(herm, sh);
+  bad = block_sum(bad, sh);
+  double tr = 0.0, ex = 0.0, ph = 0.0, nx = 0.0;
+  for (int64_t s = threadIdx.x; s < N; s += TPB) {
+    const double d = diag[s];
+    const int pc = popc64(uint64_t(s) & mask);
+    const int64_t mm = s >> n;
+    tr += d;
+    ex += double(pc) * d;
+    ph += double(mm) * d;
+    nx += double(mm + pc) * d;
+  }
+  tr = block_sum(tr, sh);
+  ex = block_sum(ex, sh);
+  ph = block_sum(ph, sh);
+  nx = block_sum(nx, sh);
+  if (threadIdx.x == 0) {
+    scalars[0] = tr;
+    scalars[1] = trace_im_src ? *trace_im_src : 0.0;
+    scalars[2] = pur;
+    scalars[3] = herm;
+    scalars[4] = ex;
+    scalars[5] = ph;
+    scalars[6] = nx;
+    scalars[7] = bad > 0.0 ? 1.0 : 0.0;
+  }
+  if (atom_pop) {
+    for (int i = 0; i < n; ++i) {
+      double p = 0.0;
+      for (int64_t s = threadIdx.x; s < N; s += TPB)
+        if ((uint64_t(s) >> (n - 1 - i)) & 1) p += diag[s];
+      p = block_sum(p, sh);
+      if (threadIdx.x == 0) atom_pop[i] = p;
+    }
+  }
+  if (photon_dist) {
+    const int64_t per = int64_t(1) << n;
+    for (int mm = 0; mm <= m.c; ++mm) {
+      double p = 0.0;
+      for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) p += diag[s];
+      p = block_sum(p, sh);
+      if (threadIdx.x == 0) photon_dist[mm] = p;
+    }
+  }
+  if (exc_dist) {
+    for (int k = 0; k <= n + m.c; ++k) {
+      double p = 0.0;
+      for (int64_t s = threadIdx.x; s < N; s += TPB)
+        if (int(s >> n) + popc64(uint64_t(s) & mask) == k) p += diag[s];
+      p = block_sum(p, sh);
+      if (threadIdx.x == 0) exc_dist[k] = p;
+    }
+  }
+}
+
+// Im Tr rho (separate, one block).
+template <typename E>
+__global__ void trace_im_kernel(const E* __restrict__ rho, int64_t ld, int64_t N, double* out) {
+  __shared__ double sh[TPB];
+  double part = 0.0;
+  for (int64_t s = threadIdx.x; s < N; s += TPB) part += double(rho[s * ld + s].im);
+  const double t = block_sum(part, sh);
+  if (threadIdx.x == 0) *out = t;
+}
+
+// --------------------------------------------------------- bfloat16 split
+__device__ __forceinline__ uint16_t rne_bf16(float x) {
+  const uint32_t b = __float_as_uint(x);
+  if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu) != 0)
+    return uint16_t((b >> 16) | 0x40u);                       // NaN stays (quiet) NaN
+  const uint32_t upper = b >> 16, rem = b & 0xFFFFu;
+  const uint32_t up = (rem > 0x8000u) || (rem == 0x8000u && (upper & 1u));
+  return uint16_t(upper + up);
+}
+
+__global__ void split_bf16_kernel(const float* __restrict__ x, int64_t count,
+                                  uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * TPB) {
+    const float v = x[i];
+    const uint16_t h = rne_bf16(v);
+    const float r = v - __uint_as_float(uint32_t(h) << 16);
+    hi[i] = h;
+    lo[i] = rne_bf16(r);
+  }
+}
+
+dim3 grid2(int64_t cols, int64_t rows) {
+  const int64_t gx = (cols + TPB - 1) / TPB;
+  const int64_t gy = rows < 4096 ? rows : 4096;
+  return dim3(unsigned(gx > 0 ? gx : 1), unsigned(gy > 0 ? gy : 1));
+}
+
+int64_t npairs_of(int64_t N) {
+  const int64_t T = (N + RT - 1) / RT;
+  return T * (T + 1) / 2;
+}
+
+}  // namespace
+
+int launch_ham_fill(const ModelArgs& m, double* H, int64_t ldh, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(ham_fill_kernel, grid2(m.N, m.N), dim3(TPB), 0, s, m, H, ldh);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_axpb_identity(const double* X, int64_t ldx, double a, double b, double* out,
+                         int64_t ldo, int64_t N, hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(axpb_identity_kernel, grid2(N, N), dim3(TPB), 0, s, X, ldx, a, b, out, ldo, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_assemble_cs(const double* Cm, const double* Sm, int64_t ld, double pr, double pi,
+                       c128* U, int64_t ldu, int64_t N, hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(assemble_cs_kernel, grid2(N, N), dim3(TPB), 0, s, Cm, Sm, ld, pr, pi, U, ldu, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_symmetrize(c128* U, int64_t ldu, int64_t N, hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(symmetrize_kernel, grid2(N, N), dim3(TPB), 0, s, U, ldu, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_copy_c128_to_c64(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows,
+                            int64_t cols, hipStream_t s) {
+  if (rows == 0 || cols == 0) return TC_OK;
+  hipLaunchKernelGGL(c128_to_c64_kernel, grid2(cols, rows), dim3(TPB), 0, s, src, lds, dst, ldd, rows, cols);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_copy_c64_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows,
+                            int64_t cols, hipStream_t s) {
+  if (rows == 0 || cols == 0) return TC_OK;
+  hipLaunchKernelGGL(c64_to_c128_kernel, grid2(cols, rows), dim3(TPB), 0, s, src, lds, dst, ldd, rows, cols);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_rotating_d(const ModelArgs& m, const c128* U, int64_t ldu, double dt, c128* D,
+                      int64_t ldd, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(rotating_d_kernel<c128>, grid2(m.N, m.N), dim3(TPB), 0, s, m, U, ldu, dt, D, ldd);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_rotating_d_c64(const ModelArgs& m, const c128* U, int64_t ldu, double dt, c64* D,
+                          int64_t ldd, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(rotating_d_kernel<c64>, grid2(m.N, m.N), dim3(TPB), 0, s, m, U, ldu, dt, D, ldd);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_frame_phase_c128(const ModelArgs& m, c128* rho, int64_t ld, double t, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(frame_phase_kernel<c128>, grid2(m.N, m.N), dim3(TPB), 0, s, m, rho, ld, t);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_frame_phase_c64(const ModelArgs& m, c64* rho, int64_t ld, double t, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(frame_phase_kernel<c64>, grid2(m.N, m.N), dim3(TPB), 0, s, m, rho, ld, t);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,
+                        double* pdist, hipStream_t s) {
+  hipLaunchKernelGGL(readout_kernel<c128>, dim3(1), dim3(TPB), 0, s, m, rho, ld, pop, pdist);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
+                       double* pdist, hipStream_t s) {
+  hipLaunchKernelGGL(readout_kernel<c64>, dim3(1), dim3(TPB), 0, s, m, rho, ld, pop, pdist);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+template <typename E>
+static int renorm_impl(E* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(trace_kernel<E>, dim3(1), dim3(TPB), 0, s, rho, ld, N, scratch);
+  TC_TRY_HIP(hipGetLastError());
+  const int64_t np = npairs_of(N);
+  hipLaunchKernelGGL(renorm_kernel<E>, dim3(unsigned(np)), dim3(TPB), 0, s, rho, ld, N, scratch);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_renorm_c128(c128* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s) {
+  return renorm_impl(rho, ld, N, scratch, s);
+}
+int launch_renorm_c64(c64* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s) {
+  return renorm_impl(rho, ld, N, scratch, s);
+}
+
+size_t observables_partials_count(int64_t N) {
+  return size_t(3 * npairs_of(N) + N + 8);
+}
+
+int launch_observables(const ModelArgs& m, const void* rho, int dtype, int64_t ld,
+                       double* partials, double* scalars, double* atom_pop,
+                       double* photon_dist, double* exc_dist, hipStream_t s) {
+  const int64_t N = m.N;
+  const int64_t np = npairs_of(N);
+  double* diag = partials + 3 * np;
+  double* tim = diag + N;
+  if (dtype == TC_C128) {
+    const c128* r = static_cast<const c128*>(rho);
+    hipLaunchKernelGGL(obs_pass1<c128>, dim3(unsigned(np)), dim3(TPB), 0, s, r, ld, N, partials, diag);
+    hipLaunchKernelGGL(trace_im_kernel<c128>, dim3(1), dim3(TPB), 0, s, r, ld, N, tim);
+  } else {
+    const c64* r = static_cast<const c64*>(rho);
+    hipLaunchKernelGGL(obs_pass1<c64>, dim3(unsigned(np)), dim3(TPB), 0, s, r, ld, N, partials, diag);
+    hipLaunchKernelGGL(trace_im_kernel<c64>, dim3(1), dim3(TPB), 0, s, r, ld, N, tim);
+  }
+  TC_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(obs_pass2, dim3(1), dim3(TPB), 0, s, m, partials, np, diag, tim, scalars,
+                     atom_pop, photon_dist, exc_dist);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+  if (count == 0) return TC_OK;
+  int64_t blocks = (count + TPB - 1) / TPB;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3(unsigned(blocks)), dim3(TPB), 0, s, x, count, hi, lo);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+}  // namespace tcm

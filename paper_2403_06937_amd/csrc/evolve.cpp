@@ -1,0 +1,430 @@
+// tc_evolve: the time-stepping loop rho <- U rho U^dag (Eq. (6)) with readouts,
+// renormalisation, checkpoints and the frame change; plus tc_observables,
+// tc_zgemm and tc_split_bf16.
+#include <cmath>
+#include <string>
+#include <vector>
+#include <algorithm>
+
+#include "common.h"
+#include "gemm_mfma.h"
+#include "gemm_bf16.h"
+#include "kernels.h"
+
+namespace tcm {
+namespace {
+
+size_t elem_bytes(int dtype) { return dtype == TC_C128 ? 16 : 8; }
+
+// Buffers of one instance, carved from the workspace.
+struct InstPlan {
+  ModelArgs m;
+  int64_t N = 0;
+  // product operand (U in the lab frame, D = U~ - I in the rotating frame)
+  const void* op = nullptr; int64_t ldop = 0;
+  void* op_own = nullptr;       // workspace copy when converted
+  // master state (c128 for F64, c64 for F32 / split)
+  void* rho = nullptr; int64_t ldr = 0;
+  bool rho_converted = false;
+  void* X = nullptr; int64_t ldx = 0;
+  double* scratch = nullptr;    // [4]: trace, non-finite flag, ...
+  SplitPlanes planes;           // split-BF16 operand planes
+};
+
+int validate_opts(const tc_evolve_opts* o) {
+  TC_CHECK_ARG(o != nullptr, "opts is NULL");
+  TC_CHECK_ARG(o->steps >= 0, "steps < 0");
+  TC_CHECK_ARG(o->gemm_mode == TC_GEMM_F64 || o->gemm_mode == TC_GEMM_F32 ||
+               o->gemm_mode == TC_GEMM_SPLIT_BF16, "unknown gemm_mode");
+  TC_CHECK_ARG(o->rho_dtype == TC_C64 || o->rho_dtype == TC_C128, "unknown rho_dtype");
+  TC_CHECK_ARG(o->frame == TC_FRAME_LAB || o->frame == TC_FRAME_ROTATING, "unknown frame");
+  TC_CHECK_ARG(o->renorm_every >= 0, "renorm_every < 0");
+  TC_CHECK_ARG(o->record_every >= 0, "record_every < 0");
+  TC_CHECK_ARG(o->checkpoint_every >= 0, "checkpoint_every < 0");
+  TC_CHECK_ARG(std::isfinite(o->dt), "dt not finite");
+  return TC_OK;
+}
+
+int validate_instance(const tc_instance* in, const tc_evolve_opts* o, ModelArgs* m) {
+  TC_CHECK_ARG(in != nullptr, "instance is NULL");
+  TC_RETURN_IF(make_model_args(in->model, m));
+  TC_CHECK_ARG(in->N == m->N, "instance N != (c+1) 2^n");
+  TC_CHECK_ARG(in->U != nullptr && in->rho != nullptr, "U / rho is NULL");
+  TC_CHECK_ARG(in->ldu >= in->N && in->ldr >= in->N, "leading dimension < N");
+  if (in->pop_out || in->photon_dist_out)
+    TC_CHECK_ARG(o->record_every >= 1, "record_every must be >= 1 when records are requested");
+  if (in->checkpoints)
+    TC_CHECK_ARG(o->checkpoint_every >= 1, "checkpoint_every must be >= 1 with checkpoints");
+  return TC_OK;
+}
+
+// Lays out (or sizes, when ar.base == nullptr) the workspace of one instance.
+void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelArgs& m, Arena& ar,
+                   InstPlan* p) {
+  const int64_t N = in.N;
+  const size_t NN = size_t(N) * size_t(N);
+  p->m = m;
+  p->N = N;
+  p->scratch = static_cast<double*>(ar.take(4 * sizeof(double)));
+  if (o.gemm_mode == TC_GEMM_F64) {
+    if (o.rho_dtype == TC_C128) {
+      p->rho = in.rho; p->ldr = in.ldr; p->rho_converted = false;
+    } else {
+      p->rho = ar.take(NN * 16); p->ldr = N; p->rho_converted = true;
+    }
+    if (o.frame == TC_FRAME_LAB) {
+      p->op = in.U; p->ldop = in.ldu;
+    } else {
+      p->op_own = ar.take(NN * 16); p->op = p->op_own; p->ldop = N;
+    }
+    p->X = ar.take(NN * 16); p->ldx = N;
+  } else {
+    // FP32 and split-BF16 keep an FP32 master
+    if (o.rho_dtype == TC_C64) {
+      p->rho = in.rho; p->ldr = in.ldr; p->rho_converted = false;
+    } else {
+      p->rho = ar.take(NN * 8); p->ldr = N; p->rho_converted = true;
+    }
+    p->op_own = ar.take(NN * 8); p->op = p->op_own; p->ldop = N;
+    p->X = ar.take(NN * 8); p->ldx = N;
+    if (o.gemm_mode == TC_GEMM_SPLIT_BF16) split_plan(ar, N, &p->planes);
+  }
+}
+
+int readout(const InstPlan& p, const tc_evolve_opts& o, double* pop, double* pdist,
+            hipStream_t s) {
+  if (o.gemm_mode == TC_GEMM_F64)
+    return launch_readout_c128(p.m, static_cast<const c128*>(p.rho), p.ldr, pop, pdist, s);
+  return launch_readout_c64(p.m, static_cast<const c64*>(p.rho), p.ldr, pop, pdist, s);
+}
+
+int renorm(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (o.gemm_mode == TC_GEMM_F64)
+    return launch_renorm_c128(static_cast<c128*>(p.rho), p.ldr, p.N, p.scratch, s);
+  TC_RETURN_IF(launch_renorm_c64(static_cast<c64*>(p.rho), p.ldr, p.N, p.scratch, s));
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
+    TC_RETURN_IF(split_state(static_cast<const c64*>(p.rho), p.ldr, p.N, p.planes, s));
+  return TC_OK;
+}
+
+// One step of Eq. (6) for FP64 / FP32:
+//   lab:      X = U rho,          rho' = X U^dag = X conj(U)   (U symmetric)
+//   rotating: X = rho + D rho,    rho' = X + X conj(D)         (U~ = I + D symmetric)
+int step_mfma(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  const bool rot = o.frame == TC_FRAME_ROTATING;
+  GemmDesc g1;
+  g1.M = g1.N = g1.K = p.N;
+  g1.A = p.op; g1.lda = p.ldop; g1.a_kmaj = false;
+  g1.B = p.rho; g1.ldb = p.ldr; g1.b_kmaj = true;
+  g1.C = p.X; g1.ldc = p.ldx;
+  if (rot) { g1.Cin = p.rho; g1.ldcin = p.ldr; g1.beta_re = 1.0; }
+  GemmDesc g2;
+  g2.M = g2.N = g2.K = p.N;
+  g2.A = p.X; g2.lda = p.ldx; g2.a_kmaj = false;
+  g2.B = p.op; g2.ldb = p.ldop; g2.b_kmaj = true; g2.conj_b = true;
+  g2.C = p.rho; g2.ldc = p.ldr;
+  if (rot) { g2.Cin = p.X; g2.ldcin = p.ldx; g2.beta_re = 1.0; }
+  if (o.gemm_mode == TC_GEMM_F64) {
+    TC_RETURN_IF(gemm_f64(g1, s));
+    TC_RETURN_IF(gemm_f64(g2, s));
+  } else {
+    TC_RETURN_IF(gemm_f32(g1, s));
+    TC_RETURN_IF(gemm_f32(g2, s));
+  }
+  return TC_OK;
+}
+
+int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, int64_t slot,
+                    double t, hipStream_t s) {
+  const size_t eb = elem_bytes(o.rho_dtype);
+  const size_t NN = size_t(p.N) * size_t(p.N);
+  char* dst = static_cast<char*>(in.checkpoints) + size_t(slot) * NN * eb;
+  const bool master128 = o.gemm_mode == TC_GEMM_F64;
+  if (master128 && o.rho_dtype == TC_C128) {
+    TC_TRY_HIP(hipMemcpy2DAsync(dst, p.N * 16, p.rho, p.ldr * 16, p.N * 16, p.N,
+                                hipMemcpyDeviceToDevice, s));
+  } else if (!master128 && o.rho_dtype == TC_C64) {
+    TC_TRY_HIP(hipMemcpy2DAsync(dst, p.N * 8, p.rho, p.ldr * 8, p.N * 8, p.N,
+                                hipMemcpyDeviceToDevice, s));
+  } else if (master128) {
+    TC_RETURN_IF(launch_copy_c128_to_c64(static_cast<const c128*>(p.rho), p.ldr,
+                                         reinterpret_cast<c64*>(dst), p.N, p.N, p.N, s));
+  } else {
+    TC_RETURN_IF(launch_copy_c64_to_c128(static_cast<const c64*>(p.rho), p.ldr,
+                                         reinterpret_cast<c128*>(dst), p.N, p.N, p.N, s));
+  }
+  if (o.frame == TC_FRAME_ROTATING && t != 0.0) {
+    if (o.rho_dtype == TC_C128)
+      TC_RETURN_IF(launch_frame_phase_c128(p.m, reinterpret_cast<c128*>(dst), p.N, t, s));
+    else
+      TC_RETURN_IF(launch_frame_phase_c64(p.m, reinterpret_cast<c64*>(dst), p.N, t, s));
+  }
+  return TC_OK;
+}
+
+int prepare(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
+  // master state
+  if (p.rho_converted) {
+    if (o.gemm_mode == TC_GEMM_F64)
+      TC_RETURN_IF(launch_copy_c64_to_c128(static_cast<const c64*>(in.rho), in.ldr,
+                                           static_cast<c128*>(p.rho), p.ldr, p.N, p.N, s));
+    else
+      TC_RETURN_IF(launch_copy_c128_to_c64(static_cast<const c128*>(in.rho), in.ldr,
+                                           static_cast<c64*>(p.rho), p.ldr, p.N, p.N, s));
+  }
+  // product operand
+  const c128* U = reinterpret_cast<const c128*>(in.U);
+  if (o.gemm_mode == TC_GEMM_F64) {
+    if (o.frame == TC_FRAME_ROTATING)
+      TC_RETURN_IF(launch_rotating_d(p.m, U, in.ldu, o.dt, static_cast<c128*>(p.op_own), p.ldop, s));
+  } else {
+    if (o.frame == TC_FRAME_ROTATING)
+      TC_RETURN_IF(launch_rotating_d_c64(p.m, U, in.ldu, o.dt, static_cast<c64*>(p.op_own), p.ldop, s));
+    else
+      TC_RETURN_IF(launch_copy_c128_to_c64(U, in.ldu, static_cast<c64*>(p.op_own), p.ldop, p.N, p.N, s));
+  }
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16) {
+    TC_RETURN_IF(split_operand(static_cast<const c64*>(p.op), p.ldop, p.N, p.planes, s));
+    TC_RETURN_IF(split_state(static_cast<const c64*>(p.rho), p.ldr, p.N, p.planes, s));
+  }
+  return TC_OK;
+}
+
+int finish(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  const double T = double(o.steps) * o.dt;
+  if (o.frame == TC_FRAME_ROTATING && T != 0.0) {
+    if (o.gemm_mode == TC_GEMM_F64)
+      TC_RETURN_IF(launch_frame_phase_c128(p.m, static_cast<c128*>(p.rho), p.ldr, T, s));
+    else
+      TC_RETURN_IF(launch_frame_phase_c64(p.m, static_cast<c64*>(p.rho), p.ldr, T, s));
+  }
+  if (p.rho_converted) {
+    if (o.gemm_mode == TC_GEMM_F64)
+      TC_RETURN_IF(launch_copy_c128_to_c64(static_cast<const c128*>(p.rho), p.ldr,
+                                           static_cast<c64*>(in.rho), in.ldr, p.N, p.N, s));
+    else
+      TC_RETURN_IF(launch_copy_c64_to_c128(static_cast<const c64*>(p.rho), p.ldr,
+                                           static_cast<c128*>(in.rho), in.ldr, p.N, p.N, s));
+  }
+  return TC_OK;
+}
+
+int step(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
+    return step_split(static_cast<c64*>(p.rho), p.ldr, static_cast<c64*>(p.X), p.ldx, p.N,
+                      o.frame == TC_FRAME_ROTATING, p.planes, s);
+  return step_mfma(p, o, s);
+}
+
+int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  TC_RETURN_IF(prepare(p, in, o, s));
+  const int c1 = p.m.c + 1;
+  const bool rec = (in.pop_out || in.photon_dist_out);
+  if (rec) TC_RETURN_IF(readout(p, o, in.pop_out, in.photon_dist_out, s));
+  if (in.checkpoints) TC_RETURN_IF(copy_checkpoint(p, in, o, 0, 0.0, s));
+  for (int64_t st = 1; st <= o.steps; ++st) {
+    TC_RETURN_IF(step(p, o, s));
+    if (o.renorm_every > 0 && st % o.renorm_every == 0) TC_RETURN_IF(renorm(p, o, s));
+    if (rec && st % o.record_every == 0) {
+      const int64_t r = st / o.record_every;
+      TC_RETURN_IF(readout(p, o, in.pop_out ? in.pop_out + r : nullptr,
+                           in.photon_dist_out ? in.photon_dist_out + r * c1 : nullptr, s));
+    }
+    if (in.checkpoints && st % o.checkpoint_every == 0)
+      TC_RETURN_IF(copy_checkpoint(p, in, o, st / o.checkpoint_every, double(st) * o.dt, s));
+  }
+  return finish(p, in, o, s);
+}
+
+}  // namespace
+}  // namespace tcm
+
+using namespace tcm;
+
+extern "C" {
+
+int tc_evolve_workspace_size(const tc_instance* inst, int32_t count, const tc_evolve_opts* o,
+                             size_t* bytes) {
+  clear_error();
+  TC_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+  TC_CHECK_ARG(count >= 1, "count < 1");
+  TC_CHECK_ARG(inst != nullptr, "instances is NULL");
+  TC_RETURN_IF(validate_opts(o));
+  Arena ar(nullptr, 0);
+  for (int b = 0; b < count; ++b) {
+    ModelArgs m;
+    TC_RETURN_IF(validate_instance(&inst[b], o, &m));
+    InstPlan p;
+    plan_instance(inst[b], *o, m, ar, &p);
+  }
+  *bytes = ar.used;
+  return TC_OK;
+}
+
+int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o, void* ws,
+              size_t ws_bytes, void* stream) {
+  clear_error();
+  size_t need = 0;
+  TC_RETURN_IF(tc_evolve_workspace_size(inst, count, o, &need));
+  TC_CHECK_ARG(ws != nullptr || need == 0, "workspace is NULL");
+  if (ws_bytes < need) {
+    set_error("workspace too small for tc_evolve: need " + std::to_string(need) + " bytes");
+    return TC_ERR_WORKSPACE;
+  }
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  std::vector<InstPlan> plans(count);
+  for (int b = 0; b < count; ++b) {
+    ModelArgs m;
+    TC_RETURN_IF(validate_instance(&inst[b], o, &m));
+    plan_instance(inst[b], *o, m, ar, &plans[b]);
+  }
+  for (int b = 0; b < count; ++b) TC_RETURN_IF(evolve_one(plans[b], inst[b], *o, s));
+  if (o->renorm_every > 0 && o->steps >= o->renorm_every) {
+    // one flag read per call: a renormalisation met a non-finite or non-positive trace
+    for (int b = 0; b < count; ++b) {
+      double flag = 0.0;
+      TC_TRY_HIP(hipMemcpyAsync(&flag, plans[b].scratch + 1, sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+      TC_TRY_HIP(hipStreamSynchronize(s));
+      if (flag != 0.0) {
+        set_error("renormalisation found a non-finite or non-positive trace (instance " +
+                  std::to_string(b) + ")");
+        return TC_ERR_NONFINITE;
+      }
+    }
+  }
+  return TC_OK;
+}
+
+int tc_observables_workspace_size(int64_t N, size_t* bytes) {
+  clear_error();
+  TC_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+  TC_CHECK_ARG(N >= 0, "N < 0");
+  *bytes = observables_partials_count(N) * sizeof(double);
+  return TC_OK;
+}
+
+int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype, int64_t N, int64_t ldr,
+                   double* scalars, double* atom_pop, double* photon_dist, double* exc_dist,
+                   void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  ModelArgs a;
+  TC_RETURN_IF(make_model_args(m, &a));
+  TC_CHECK_ARG(N == a.N, "N != (c+1) 2^n");
+  TC_CHECK_ARG(rho != nullptr && scalars != nullptr, "rho / scalars is NULL");
+  TC_CHECK_ARG(rho_dtype == TC_C64 || rho_dtype == TC_C128, "unknown rho_dtype");
+  TC_CHECK_ARG(ldr >= N, "ldr < N");
+  size_t need = 0;
+  TC_RETURN_IF(tc_observables_workspace_size(N, &need));
+  TC_CHECK_ARG(ws != nullptr, "workspace is NULL");
+  if (ws_bytes < need) {
+    set_error("workspace too small for tc_observables");
+    return TC_ERR_WORKSPACE;
+  }
+  return launch_observables(a, rho, rho_dtype, ldr, static_cast<double*>(ws), scalars, atom_pop,
+                            photon_dist, exc_dist, as_stream(stream));
+}
+
+int tc_gemm_workspace_size(int64_t M, int64_t N, int64_t K, int32_t mode, size_t* bytes) {
+  clear_error();
+  TC_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+  TC_CHECK_ARG(M >= 0 && N >= 0 && K >= 0, "negative size");
+  TC_CHECK_ARG(mode == TC_GEMM_F64 || mode == TC_GEMM_F32 || mode == TC_GEMM_SPLIT_BF16,
+               "unknown mode");
+  if (mode == TC_GEMM_F64) { *bytes = 0; return TC_OK; }
+  // c64 copies of A (M x K), B (K x N) and C (M x N), plus split planes
+  Arena ar(nullptr, 0);
+  ar.take(size_t(M) * size_t(K) * 8);
+  ar.take(size_t(K) * size_t(N) * 8);
+  ar.take(size_t(M) * size_t(N) * 8);
+  if (mode == TC_GEMM_SPLIT_BF16) split_gemm_plan(ar, M, N, K, nullptr);
+  *bytes = ar.used;
+  return TC_OK;
+}
+
+int tc_zgemm(int64_t M, int64_t N, int64_t K, tc_c128 alpha, const tc_c128* A, int64_t lda,
+             int32_t op_a, const tc_c128* B, int64_t ldb, int32_t op_b, tc_c128 beta, tc_c128* C,
+             int64_t ldc, int32_t mode, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  TC_CHECK_ARG(M >= 0 && N >= 0 && K >= 0, "negative size");
+  TC_CHECK_ARG(op_a >= 0 && op_a <= 3 && op_b >= 0 && op_b <= 3, "op must be 0..3");
+  TC_CHECK_ARG(C != nullptr, "C is NULL");
+  TC_CHECK_ARG(K == 0 || (A != nullptr && B != nullptr), "A / B is NULL");
+  const bool ta = op_a >= 2, tb = op_b >= 2;
+  TC_CHECK_ARG(lda >= std::max<int64_t>(1, ta ? M : K), "lda too small");
+  TC_CHECK_ARG(ldb >= std::max<int64_t>(1, tb ? K : N), "ldb too small");
+  TC_CHECK_ARG(ldc >= std::max<int64_t>(1, N), "ldc too small");
+  size_t need = 0;
+  TC_RETURN_IF(tc_gemm_workspace_size(M, N, K, mode, &need));
+  if (need) {
+    TC_CHECK_ARG(ws != nullptr, "workspace is NULL");
+    if (ws_bytes < need) { set_error("workspace too small for tc_zgemm"); return TC_ERR_WORKSPACE; }
+  }
+  hipStream_t s = as_stream(stream);
+  GemmDesc d;
+  d.M = M; d.N = N; d.K = K;
+  d.a_kmaj = ta; d.conj_a = (op_a & 1) != 0;
+  d.b_kmaj = !tb; d.conj_b = (op_b & 1) != 0;
+  d.alpha_re = alpha.re; d.alpha_im = alpha.im;
+  d.beta_re = beta.re; d.beta_im = beta.im;
+  if (mode == TC_GEMM_F64) {
+    d.A = A; d.lda = lda; d.B = B; d.ldb = ldb;
+    d.C = C; d.ldc = ldc; d.Cin = C; d.ldcin = ldc;
+    return gemm_f64(d, s);
+  }
+  // reduced precision: operate on c64 copies
+  Arena ar(ws, ws_bytes);
+  const int64_t ar_rows = ta ? K : M, ar_cols = ta ? M : K;
+  const int64_t br_rows = tb ? N : K, br_cols = tb ? K : N;
+  c64* A32 = static_cast<c64*>(ar.take(size_t(M) * size_t(K) * 8));
+  c64* B32 = static_cast<c64*>(ar.take(size_t(K) * size_t(N) * 8));
+  c64* C32 = static_cast<c64*>(ar.take(size_t(M) * size_t(N) * 8));
+  if (K > 0) {
+    TC_RETURN_IF(launch_copy_c128_to_c64(reinterpret_cast<const c128*>(A), lda, A32, ar_cols,
+                                         ar_rows, ar_cols, s));
+    TC_RETURN_IF(launch_copy_c128_to_c64(reinterpret_cast<const c128*>(B), ldb, B32, br_cols,
+                                         br_rows, br_cols, s));
+  }
+  TC_RETURN_IF(launch_copy_c128_to_c64(reinterpret_cast<const c128*>(C), ldc, C32, N, M, N, s));
+  d.A = A32; d.lda = ar_cols; d.B = B32; d.ldb = br_cols;
+  d.C = C32; d.ldc = N; d.Cin = C32; d.ldcin = N;
+  if (mode == TC_GEMM_F32) {
+    TC_RETURN_IF(gemm_f32(d, s));
+  } else {
+    SplitGemmPlan sp;
+    split_gemm_plan(ar, M, N, K, &sp);
+    TC_RETURN_IF(split_gemm(d, sp, s));
+  }
+  return launch_copy_c64_to_c128(C32, N, reinterpret_cast<c128*>(C), ldc, M, N, s);
+}
+
+int tc_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, void* stream) {
+  clear_error();
+  TC_CHECK_ARG(count >= 0, "count < 0");
+  TC_CHECK_ARG(count == 0 || (x && hi && lo), "NULL pointer");
+  return launch_split_bf16(x, count, hi, lo, as_stream(stream));
+}
+
+int tc_evolve_backward_workspace_size(const tc_model* m, int64_t N, const tc_evolve_opts* o,
+                                      size_t* bytes) {
+  clear_error();
+  (void)m; (void)N; (void)o; (void)bytes;
+  set_error("tc_evolve_backward is not available in this build");
+  return TC_ERR_UNSUPPORTED;
+}
+
+int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc_c128* U,
+                       int64_t ldu, int64_t N, const tc_evolve_opts* o, const void* checkpoints,
+                       int32_t observable, double* loss_out, double* grad_g, double* grad_delta,
+                       void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  (void)m; (void)H; (void)ldh; (void)U; (void)ldu; (void)N; (void)o; (void)checkpoints;
+  (void)observable; (void)loss_out; (void)grad_g; (void)grad_delta; (void)ws; (void)ws_bytes;
+  (void)stream;
+  set_error("tc_evolve_backward is not available in this build");
+  return TC_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,375 @@
+// Split-BF16 complex matrix products on gfx950 BF16 MFMA (v_mfma_f32_16x16x32_bf16).
+//
+// Operands are four bfloat16 planes (Re hi, Re lo, Im hi, Im lo), each stored
+// with K contiguous: rows of A are its M rows, rows of B are its N columns.
+// For one 16 x 16 output block and a 32-deep K slice the kernel issues
+//   Re += Ar_h Br_h + Ar_h Br_l + Ar_l Br_h - Ai_h Bi_h - Ai_h Bi_l - Ai_l Bi_h
+//   Im += Ar_h Bi_h + Ar_h Bi_l + Ar_l Bi_h + Ai_h Br_h + Ai_h Br_l + Ai_l Br_h
+// (lo*lo dropped), twelve MFMAs, accumulating in FP32 from zero.  The minus
+// sign is a sign-bit flip of the Ai fragments in registers.
+//
+// Lane layout of v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8(l/16) .. +7]
+// and B[8(l/16) .. +7][l%16] (eight consecutive K values, one 16-byte LDS
+// read) and holds D[4(l/16)+r][l%16], r = 0..3.
+//
+// Tiling: 256 threads, 128 x 128 outputs per workgroup, 2 x 2 waves of 64 x 64
+// (4 x 4 blocks), K tile 32, all eight planes double-buffered in LDS (128 KB).
+// 16-byte chunks are XOR-swizzled by row so that the 16 rows a wave reads at
+// one K offset hit distinct LDS banks.  Tile order as in the FP64 kernel:
+// XCD-contiguous ranges walked in groups of 8 tile rows.
+//
+// The epilogue forms alpha * acc + beta * Cin in FP32 and writes any of: the
+// FP32 result, and the hi/lo planes of the result (row-major or transposed)
+// for the next product.
+#include "gemm_bf16.h"
+#include "profile.h"
+
+namespace tcm {
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint16_t rne_bf16(float x) {
+  const uint32_t b = __float_as_uint(x);
+  if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu) != 0)
+    return uint16_t((b >> 16) | 0x40u);
+  const uint32_t upper = b >> 16, rem = b & 0xFFFFu;
+  const uint32_t up = (rem > 0x8000u) || (rem == 0x8000u && (upper & 1u));
+  return uint16_t(upper + up);
+}
+__device__ __forceinline__ void split2(float x, uint16_t& h, uint16_t& l) {
+  h = rne_bf16(x);
+  l = rne_bf16(x - __uint_as_float(uint32_t(h) << 16));
+}
+
+__device__ __forceinline__ f4 mma(const u4& a, const u4& b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                 __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+
+struct SplitParams {
+  const uint16_t* A; int64_t lda, a_ps;
+  const uint16_t* B; int64_t ldb, b_ps;
+  int64_t M, N, Kp;
+  float ar, ai, br, bi;
+  const c64* Cin; int64_t ldcin; int cin_trans;
+  c64* Cf; int64_t ldcf;
+  uint16_t* P; int64_t ldp, p_ps; int p_trans;
+  int tiles_m, tiles_n;
+};
+
+constexpr int GROUP_M = 8;
+
+__device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int total = tiles_m * tiles_n;
+  const int q = total / 8, r = total % 8;
+  const int xcd = pid % 8, local = pid / 8;
+  const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+  const int per_group = GROUP_M * tiles_n;
+  const int group = lin / per_group;
+  const int first_m = group * GROUP_M;
+  const int gsize = min(tiles_m - first_m, GROUP_M);
+  const int in_group = lin % per_group;
+  tm = first_m + in_group % gsize;
+  tn = in_group / gsize;
+}
+
+__global__ void __launch_bounds__(256, 1) split_gemm_kernel(SplitParams p) {
+  // [buf][plane][row][chunk]: 16-byte chunks, 4 per 32-deep row
+  __shared__ u4 sA[2][4][SPLIT_BM][4];
+  __shared__ u4 sB[2][4][SPLIT_BN][4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int tm, tn;
+  tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int64_t m0 = int64_t(tm) * SPLIT_BM, n0 = int64_t(tn) * SPLIT_BN;
+
+  // staging: 8 planes x 128 rows x 4 chunks = 4096 chunks, 16 per thread
+  u4 st[16];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j;
+      const int pl = e >> 9;              // 0..7 (warp-uniform per j)
+      const int r = (e >> 2) & 127;
+      const int c = e & 3;
+      const uint16_t* src = pl < 4
+          ? p.A + pl * p.a_ps + (m0 + r) * p.lda + k0 + c * 8
+          : p.B + (pl - 4) * p.b_ps + (n0 + r) * p.ldb + k0 + c * 8;
+      st[j] = *reinterpret_cast<const u4*>(src);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j;
+      const int pl = e >> 9;
+      const int r = (e >> 2) & 127;
+      const int c = e & 3;
+      if (pl < 4) sA[buf][pl][r][c ^ swz(r)] = st[j];
+      else sB[buf][pl - 4][r][c ^ swz(r)] = st[j];
+    }
+  };
+
+  f4 acc_re[4][4], acc_im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc_re[i][j] = f4{0, 0, 0, 0};
+      acc_im[i][j] = f4{0, 0, 0, 0};
+    }
+
+  const int64_t ktiles = p.Kp / SPLIT_BK;
+  if (ktiles > 0) { load(0); store(0); }
+  __syncthreads();
+  const int lr = lane & 15, lc = lane >> 4;
+  const u4 sgn = u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  for (int64_t kt = 0; kt < ktiles; ++kt) {
+    const int buf = int(kt & 1);
+    if (kt + 1 < ktiles) load((kt + 1) * SPLIT_BK);
+    u4 b[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wn * 64 + j * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = sB[buf][q][row][lc ^ swz(row)];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm * 64 + i * 16 + lr;
+      u4 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = sA[buf][q][row][lc ^ swz(row)];
+      const u4 nih = a[PL_IH] ^ sgn, nil = a[PL_IL] ^ sgn;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4 re = acc_re[i][j], im = acc_im[i][j];
+        re = mma(a[PL_RH], b[j][PL_RH], re);
+        re = mma(a[PL_RH], b[j][PL_RL], re);
+        re = mma(a[PL_RL], b[j][PL_RH], re);
+        re = mma(nih, b[j][PL_IH], re);
+        re = mma(nih, b[j][PL_IL], re);
+        re = mma(nil, b[j][PL_IH], re);
+        im = mma(a[PL_RH], b[j][PL_IH], im);
+        im = mma(a[PL_RH], b[j][PL_IL], im);
+        im = mma(a[PL_RL], b[j][PL_IH], im);
+        im = mma(a[PL_IH], b[j][PL_RH], im);
+        im = mma(a[PL_IH], b[j][PL_RL], im);
+        im = mma(a[PL_IL], b[j][PL_RH], im);
+        acc_re[i][j] = re;
+        acc_im[i][j] = im;
+      }
+    }
+    if (kt + 1 < ktiles) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue
+  const bool use_beta = p.Cin != nullptr && (p.br != 0.f || p.bi != 0.f);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t row0 = m0 + wm * 64 + i * 16 + 4 * lc;
+      const int64_t col = n0 + wn * 64 + j * 16 + lr;
+      float vr[4], vi[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + r;
+        const float xr = acc_re[i][j][r], xi = acc_im[i][j][r];
+        float yr = p.ar * xr - p.ai * xi;
+        float yi = p.ar * xi + p.ai * xr;
+        const bool inb = row < p.M && col < p.N;
+        if (use_beta && inb) {
+          const c64 c = p.cin_trans ? p.Cin[col * p.ldcin + row] : p.Cin[row * p.ldcin + col];
+          yr += p.br * c.re - p.bi * c.im;
+          yi += p.br * c.im + p.bi * c.re;
+        }
+        if (!inb) { yr = 0.f; yi = 0.f; }
+        vr[r] = yr;
+        vi[r] = yi;
+        if (p.Cf && inb) p.Cf[row * p.ldcf + col] = c64{yr, yi};
+      }
+      if (p.P) {
+        uint16_t h[4][4];   // [plane][r]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          split2(vr[r], h[PL_RH][r], h[PL_RL][r]);
+          split2(vi[r], h[PL_IH][r], h[PL_IL][r]);
+        }
+        if (p.p_trans) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const u2 v = u2{uint32_t(h[q][0]) | (uint32_t(h[q][1]) << 16),
+                            uint32_t(h[q][2]) | (uint32_t(h[q][3]) << 16)};
+            *reinterpret_cast<u2*>(p.P + q * p.p_ps + col * p.ldp + row0) = v;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) p.P[q * p.p_ps + (row0 + r) * p.ldp + col] = h[q][r];
+        }
+      }
+    }
+}
+
+// out(r, c) for r < Rp, c < Cp from src (R x C valid, element (r, c) at
+// src[r*ld + c], or src[c*ld + r] when trans), conjugated if conj, zero outside.
+constexpr int ST = 32;
+__global__ void split_matrix_kernel(const c64* __restrict__ src, int64_t ld, int64_t R, int64_t C,
+                                    int trans, int conj, uint16_t* __restrict__ P, int64_t ldp,
+                                    int64_t ps) {
+  __shared__ float2 tile[ST][ST + 1];
+  const int tx = threadIdx.x % ST, ty = threadIdx.x / ST;   // 32 x 8
+  const int64_t r0 = int64_t(blockIdx.y) * ST, c0 = int64_t(blockIdx.x) * ST;
+  for (int y = ty; y < ST; y += 8) {
+    float2 v = make_float2(0.f, 0.f);
+    if (trans) {
+      // tile[y][x] = out(r0 + x, c0 + y) = src[(c0 + y) * ld + r0 + x]
+      const int64_t r = r0 + tx, c = c0 + y;
+      if (r < R && c < C) { const c64 s = src[c * ld + r]; v = make_float2(s.re, s.im); }
+    } else {
+      const int64_t r = r0 + y, c = c0 + tx;
+      if (r < R && c < C) { const c64 s = src[r * ld + c]; v = make_float2(s.re, s.im); }
+    }
+    tile[y][tx] = v;
+  }
+  __syncthreads();
+  for (int y = ty; y < ST; y += 8) {
+    const float2 v = trans ? tile[tx][y] : tile[y][tx];
+    const int64_t r = r0 + y, c = c0 + tx;
+    uint16_t rh, rl, ih, il;
+    split2(v.x, rh, rl);
+    split2(conj ? -v.y : v.y, ih, il);
+    const int64_t o = r * ldp + c;
+    P[0 * ps + o] = rh;
+    P[1 * ps + o] = rl;
+    P[2 * ps + o] = ih;
+    P[3 * ps + o] = il;
+  }
+}
+
+Planes4 take_planes(Arena& ar, int64_t rows, int64_t ld) {
+  Planes4 p;
+  p.rows = rows;
+  p.ld = ld;
+  p.pstride = rows * ld;
+  p.base = static_cast<uint16_t*>(ar.take(size_t(4) * size_t(rows) * size_t(ld) * 2));
+  return p;
+}
+
+int split_into(const c64* src, int64_t ld, int64_t R, int64_t C, bool trans, bool conj,
+               const Planes4& P, hipStream_t s) {
+  // fills all P.rows x P.ld entries (padding becomes zero)
+  dim3 grid(unsigned(P.ld / ST), unsigned(P.rows / ST));
+  hipLaunchKernelGGL(split_matrix_kernel, grid, dim3(256), 0, s, src, ld, R, C, int(trans),
+                     int(conj), P.base, P.ld, P.pstride);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t Kp, float ar,
+              float ai, float br, float bi, const c64* Cin, int64_t ldcin, bool cin_trans, c64* Cf,
+              int64_t ldcf, const Planes4* P, bool p_trans, hipStream_t s) {
+  SplitParams q;
+  q.A = A.base; q.lda = A.ld; q.a_ps = A.pstride;
+  q.B = B.base; q.ldb = B.ld; q.b_ps = B.pstride;
+  q.M = M; q.N = N; q.Kp = Kp;
+  q.ar = ar; q.ai = ai; q.br = br; q.bi = bi;
+  q.Cin = Cin; q.ldcin = ldcin; q.cin_trans = cin_trans;
+  q.Cf = Cf; q.ldcf = ldcf;
+  q.P = P ? P->base : nullptr; q.ldp = P ? P->ld : 0; q.p_ps = P ? P->pstride : 0;
+  q.p_trans = p_trans;
+  q.tiles_m = int((M + SPLIT_BM - 1) / SPLIT_BM);
+  q.tiles_n = int((N + SPLIT_BN - 1) / SPLIT_BN);
+  const int64_t tiles = int64_t(q.tiles_m) * q.tiles_n;
+  if (tiles == 0) return TC_OK;
+  // the padded planes must cover every tile row / column and the K extent
+  if (A.rows < int64_t(q.tiles_m) * SPLIT_BM || B.rows < int64_t(q.tiles_n) * SPLIT_BN ||
+      A.ld < Kp || B.ld < Kp || Kp % SPLIT_BK != 0 ||
+      (P && (P->rows < (p_trans ? int64_t(q.tiles_n) * SPLIT_BN : int64_t(q.tiles_m) * SPLIT_BM) ||
+             P->ld < (p_trans ? int64_t(q.tiles_m) * SPLIT_BM : int64_t(q.tiles_n) * SPLIT_BN)))) {
+    set_error("split product: plane buffers do not cover the padded tiles");
+    return TC_ERR_INVALID_ARGUMENT;
+  }
+  ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
+  hipLaunchKernelGGL(split_gemm_kernel, dim3(unsigned(tiles)), dim3(256), 0, s, q);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+}  // namespace
+
+void split_plan(Arena& ar, int64_t N, SplitPlanes* p) {
+  const int64_t Np = round_up(N, SPLIT_BM);   // SPLIT_BM = SPLIT_BN, multiple of SPLIT_BK
+  p->N = N;
+  p->Np = Np;
+  p->opA = take_planes(ar, Np, Np);
+  p->opB = take_planes(ar, Np, Np);
+  p->X = take_planes(ar, Np, Np);
+  p->Rt = take_planes(ar, Np, Np);
+}
+
+int split_operand(const c64* op, int64_t ld, int64_t N, const SplitPlanes& p, hipStream_t s) {
+  TC_RETURN_IF(split_into(op, ld, N, N, false, false, p.opA, s));
+  TC_RETURN_IF(split_into(op, ld, N, N, true, true, p.opB, s));
+  // X planes: their padding must be zero before the first product writes them
+  TC_TRY_HIP(hipMemsetAsync(p.X.base, 0, size_t(4) * p.X.pstride * 2, s));
+  return TC_OK;
+}
+
+int split_state(const c64* rho, int64_t ld, int64_t N, const SplitPlanes& p, hipStream_t s) {
+  return split_into(rho, ld, N, N, true, false, p.Rt, s);
+}
+
+int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotating,
+               const SplitPlanes& p, hipStream_t s) {
+  // X = op rho (+ rho): A = split(op), B = split(rho^T); planes of X row-major
+  TC_RETURN_IF(run_split(p.opA, p.Rt, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
+                         rotating ? rho : nullptr, ldr, false, rotating ? X : nullptr, ldx,
+                         &p.X, false, s));
+  // rho' = X conj(op) (+ X): A = split(X), B = split(conj(op)^T); FP32 rho and
+  // transposed planes of rho for the next step
+  TC_RETURN_IF(run_split(p.X, p.opB, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
+                         rotating ? X : nullptr, ldx, false, rho, ldr, &p.Rt, true, s));
+  return TC_OK;
+}
+
+void split_gemm_plan(Arena& ar, int64_t M, int64_t N, int64_t K, SplitGemmPlan* p) {
+  const int64_t Mp = round_up(std::max<int64_t>(M, 1), SPLIT_BM);
+  const int64_t Np = round_up(std::max<int64_t>(N, 1), SPLIT_BN);
+  const int64_t Kp = round_up(std::max<int64_t>(K, 1), SPLIT_BK);
+  Planes4 a = take_planes(ar, Mp, Kp);
+  Planes4 b = take_planes(ar, Np, Kp);
+  if (p) { p->A = a; p->B = b; }
+}
+
+int split_gemm(const GemmDesc& d, const SplitGemmPlan& p, hipStream_t s) {
+  // A planes: element (m, k) of op(A); B planes: row n holds column n of op(B)
+  const c64* A = static_cast<const c64*>(d.A);
+  const c64* B = static_cast<const c64*>(d.B);
+  if (d.K > 0) {
+    // op(A)(m, k) = A[k*lda + m] when a_kmaj: a transposed read
+    TC_RETURN_IF(split_into(A, d.lda, d.M, d.K, d.a_kmaj, d.conj_a, p.A, s));
+    // B plane row n, column k = op(B)(k, n) = B[k*ldb + n] when b_kmaj: transposed read
+    TC_RETURN_IF(split_into(B, d.ldb, d.N, d.K, d.b_kmaj, d.conj_b, p.B, s));
+  } else {
+    TC_TRY_HIP(hipMemsetAsync(p.A.base, 0, size_t(4) * p.A.pstride * 2, s));
+    TC_TRY_HIP(hipMemsetAsync(p.B.base, 0, size_t(4) * p.B.pstride * 2, s));
+  }
+  return run_split(p.A, p.B, d.M, d.N, p.A.ld, float(d.alpha_re), float(d.alpha_im),
+                   float(d.beta_re), float(d.beta_im), static_cast<const c64*>(d.Cin), d.ldcin,
+                   d.cin_trans, static_cast<c64*>(d.C), d.ldc, nullptr, false, s);
+}
+
+}  // namespace tcm

@@ -1,0 +1,34 @@
+// Dense MFMA matrix products for FP64 and FP32 (complex and real).
+#pragma once
+#include "common.h"
+
+namespace tcm {
+
+// C = alpha * op(A) op(B) + beta * Cin + gamma * I   (M x N, inner dimension K)
+//
+// Operand storage (element type: cplx<T> if complex else T):
+//   a_kmaj: element (m, k) of op(A) at A[k * lda + m]  ("K-major"),
+//           else at A[m * lda + k]                      (row-major).
+//   b_kmaj: element (k, n) of op(B) at B[k * ldb + n]   (row-major),
+//           else at B[n * ldb + k]                      ("N-major", i.e. B^T stored).
+//   conj_a / conj_b conjugate the operand while it is staged.
+//   c_trans: element (m, n) of the result goes to C[n * ldc + m] instead of
+//            C[m * ldc + n].
+//   cin_trans: element (m, n) of Cin is read from Cin[n * ldcin + m] instead of
+//            Cin[m * ldcin + n].  Cin may alias C only with the same layout.
+struct GemmDesc {
+  int64_t M = 0, N = 0, K = 0;
+  const void* A = nullptr; int64_t lda = 0; bool a_kmaj = false; bool conj_a = false;
+  const void* B = nullptr; int64_t ldb = 0; bool b_kmaj = true;  bool conj_b = false;
+  void* C = nullptr; int64_t ldc = 0; bool c_trans = false;
+  const void* Cin = nullptr; int64_t ldcin = 0; bool cin_trans = false;
+  double alpha_re = 1.0, alpha_im = 0.0;
+  double beta_re = 0.0, beta_im = 0.0;
+  double gamma = 0.0;       // added to the real part of the diagonal (m == n)
+  bool complex = true;
+};
+
+int gemm_f64(const GemmDesc& d, hipStream_t s);   // elements double / cplx<double>
+int gemm_f32(const GemmDesc& d, hipStream_t s);   // elements float / cplx<float>
+
+}  // namespace tcm

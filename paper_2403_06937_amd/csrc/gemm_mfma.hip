@@ -1,0 +1,306 @@
+// MFMA matrix products in FP64 and FP32 for gfx950 (CDNA4).
+//
+// One templated kernel covers the complex products of the time step
+// (rho <- U rho U^dag, two complex N x N x N products per step) and the real
+// and complex products used to form U.  Design:
+//   * 256 threads = 4 wavefronts of 64 lanes; the wave grid is WGM x WGN and
+//     each wave owns WM x WN blocks of 16 x 16 outputs.
+//   * v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32: lane l supplies
+//     A[l%16][l/16] and B[l/16][l%16] of a 16x4 / 4x16 slice.  Output r of
+//     lane l is D[4*(l/16)+r][l%16] for FP32 but D[l/16+4r][l%16] for FP64
+//     (measured on gfx950).  A complex block needs four real
+//     products: Re += Ar*Br - Ai*Bi, Im += Ar*Bi + Ai*Br.  For FP64 the minus
+//     sign is the instruction's own A-negation modifier.
+//   * Tiles of A and B are staged through LDS "K-major" (sA[k][m], sB[k][n]) so
+//     a wave's 16 lanes read 16 consecutive elements; two LDS buffers, one
+//     barrier per K-tile, global loads for tile t+1 in flight while tile t
+//     is multiplied.
+//   * Complex elements stay interleaved (re, im): one 16-byte LDS read gives a
+//     lane both parts of its FP64 operand.
+//   * Workgroups are renumbered so each XCD (workgroup id mod 8) owns a
+//     contiguous range of tiles, walked in groups of GROUP_M tile rows, so
+//     tiles that share A rows / B columns share that XCD's L2.
+#include "gemm_mfma.h"
+#include "profile.h"
+
+namespace tcm {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct acc_t;
+template <> struct acc_t<double> { typedef d4 type; };
+template <> struct acc_t<float> { typedef f4 type; };
+
+__device__ __forceinline__ d4 mma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// -a * b + c via the FP64 MFMA negation modifier (neg:[1,0,0]).
+__device__ __forceinline__ d4 mma_nega(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+}
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma_nega(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(-a, b, c, 0, 0, 0);
+}
+
+template <typename T, bool CPLX> struct elem;
+template <typename T> struct elem<T, true> {
+  typedef cplx<T> type;
+  static __device__ __forceinline__ type zero() { return type{T(0), T(0)}; }
+  static __device__ __forceinline__ type cj(type x, bool c) { if (c) x.im = -x.im; return x; }
+};
+template <typename T> struct elem<T, false> {
+  typedef T type;
+  static __device__ __forceinline__ type zero() { return T(0); }
+  static __device__ __forceinline__ type cj(type x, bool) { return x; }
+};
+
+struct Params {
+  int64_t M, N, K;
+  const void* A; int64_t lda;
+  const void* B; int64_t ldb;
+  void* C; int64_t ldc;
+  const void* Cin; int64_t ldcin;
+  double alpha_re, alpha_im, beta_re, beta_im, gamma;
+  int conj_a, conj_b, c_trans, cin_trans;
+  int tiles_m, tiles_n;
+};
+
+constexpr int GROUP_M = 8;
+
+// Tile coordinates of this workgroup (XCD-contiguous, grouped ordering).
+__device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int total = tiles_m * tiles_n;
+  const int q = total / 8, r = total % 8;
+  const int xcd = pid % 8, local = pid / 8;
+  const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+  const int per_group = GROUP_M * tiles_n;
+  const int group = lin / per_group;
+  const int first_m = group * GROUP_M;
+  const int gsize = min(tiles_m - first_m, GROUP_M);
+  const int in_group = lin % per_group;
+  tm = first_m + in_group % gsize;
+  tn = in_group / gsize;
+}
+
+template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
+          int BM, int BN, int BKT, int WM, int WN>
+__global__ void __launch_bounds__(256)
+gemm_kernel(Params p) {
+  typedef typename elem<T, CPLX>::type E;
+  typedef typename acc_t<T>::type A4;
+  constexpr int WGN = BN / (16 * WN);
+  constexpr int WGM = BM / (16 * WM);
+  static_assert(WGM * WGN == 4, "4 waves per workgroup");
+  static_assert(BKT % 4 == 0, "K tile is a multiple of the MFMA depth");
+  constexpr int PADE = 16 / sizeof(E) > 0 ? 16 / sizeof(E) : 1;  // 16 bytes of padding
+  constexpr int LDA_S = BM + PADE;
+  constexpr int LDB_S = BN + PADE;
+  constexpr int A_PT = BKT * BM / 256;   // staged elements per thread
+  constexpr int B_PT = BKT * BN / 256;
+  static_assert(BKT * BM % 256 == 0 && BKT * BN % 256 == 0, "tile split");
+
+  __shared__ E sA[2][BKT][LDA_S];
+  __shared__ E sB[2][BKT][LDB_S];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  int tm, tn;
+  tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+
+  const E* __restrict__ Ag = static_cast<const E*>(p.A);
+  const E* __restrict__ Bg = static_cast<const E*>(p.B);
+  const bool cja = p.conj_a, cjb = p.conj_b;
+
+  A4 acc_re[WM][WN], acc_im[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      acc_re[i][j] = A4{0, 0, 0, 0};
+      acc_im[i][j] = A4{0, 0, 0, 0};
+    }
+
+  E ra[A_PT], rb[B_PT];
+
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < A_PT; ++j) {
+      const int e = tid + 256 * j;
+      int kk, mm;
+      if (AK) { kk = e / BM; mm = e % BM; } else { kk = e % BKT; mm = e / BKT; }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      const int64_t addr = AK ? gk * p.lda + gm : gm * p.lda + gk;
+      if (CHECKED && (gm >= p.M || gk >= p.K)) ra[j] = elem<T, CPLX>::zero();
+      else ra[j] = elem<T, CPLX>::cj(Ag[addr], cja);
+    }
+#pragma unroll
+    for (int j = 0; j < B_PT; ++j) {
+      const int e = tid + 256 * j;
+      int kk, nn;
+      if (BK) { kk = e / BN; nn = e % BN; } else { kk = e % BKT; nn = e / BKT; }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      const int64_t addr = BK ? gk * p.ldb + gn : gn * p.ldb + gk;
+      if (CHECKED && (gn >= p.N || gk >= p.K)) rb[j] = elem<T, CPLX>::zero();
+      else rb[j] = elem<T, CPLX>::cj(Bg[addr], cjb);
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < A_PT; ++j) {
+      const int e = tid + 256 * j;
+      int kk, mm;
+      if (AK) { kk = e / BM; mm = e % BM; } else { kk = e % BKT; mm = e / BKT; }
+      sA[buf][kk][mm] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < B_PT; ++j) {
+      const int e = tid + 256 * j;
+      int kk, nn;
+      if (BK) { kk = e / BN; nn = e % BN; } else { kk = e % BKT; nn = e / BKT; }
+      sB[buf][kk][nn] = rb[j];
+    }
+  };
+
+  const int64_t ktiles = (p.K + BKT - 1) / BKT;
+  if (ktiles > 0) {
+    load_tiles(0);
+    store_tiles(0);
+  }
+  __syncthreads();
+
+  const int lrow = lane >> 4;   // k offset within the 4-deep slice
+  const int lcol = lane & 15;   // m / n offset within the 16-wide block
+  for (int64_t kt = 0; kt < ktiles; ++kt) {
+    const int buf = int(kt & 1);
+    if (kt + 1 < ktiles) load_tiles((kt + 1) * BKT);
+#pragma unroll
+    for (int k4 = 0; k4 < BKT / 4; ++k4) {
+      E a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i] = sA[buf][k4 * 4 + lrow][(wm * WM + i) * 16 + lcol];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j] = sB[buf][k4 * 4 + lrow][(wn * WN + j) * 16 + lcol];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          if constexpr (CPLX) {
+            acc_re[i][j] = mma(a[i].re, b[j].re, acc_re[i][j]);
+            acc_re[i][j] = mma_nega(a[i].im, b[j].im, acc_re[i][j]);
+            acc_im[i][j] = mma(a[i].re, b[j].im, acc_im[i][j]);
+            acc_im[i][j] = mma(a[i].im, b[j].re, acc_im[i][j]);
+          } else {
+            acc_re[i][j] = mma(a[i], b[j], acc_re[i][j]);
+          }
+        }
+    }
+    if (kt + 1 < ktiles) store_tiles(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: C = alpha * acc + beta * Cin + gamma * [m == n]
+  E* __restrict__ Cg = static_cast<E*>(p.C);
+  const E* __restrict__ Cin = static_cast<const E*>(p.Cin);
+  const T ar = T(p.alpha_re), ai = T(p.alpha_im), br = T(p.beta_re), bi = T(p.beta_im);
+  const T gam = T(p.gamma);
+  const bool use_beta = (Cin != nullptr) && (p.beta_re != 0.0 || p.beta_im != 0.0);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // FP64 MFMA output r of lane l is row l/16 + 4r; FP32 is row 4(l/16) + r
+        const int64_t row = m0 + (wm * WM + i) * 16 +
+                            (sizeof(T) == 8 ? lrow + 4 * r : 4 * lrow + r);
+        const int64_t col = n0 + (wn * WN + j) * 16 + lcol;
+        if (CHECKED && (row >= p.M || col >= p.N)) continue;
+        const int64_t caddr = p.c_trans ? col * p.ldc + row : row * p.ldc + col;
+        E out;
+        if constexpr (CPLX) {
+          const T xr = acc_re[i][j][r], xi = acc_im[i][j][r];
+          out.re = ar * xr - ai * xi;
+          out.im = ar * xi + ai * xr;
+          if (use_beta) {
+            const int64_t iaddr = p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col;
+            const E y = Cin[iaddr];
+            out.re += br * y.re - bi * y.im;
+            out.im += br * y.im + bi * y.re;
+          }
+          if (row == col) out.re += gam;
+        } else {
+          out = ar * acc_re[i][j][r];
+          if (use_beta) {
+            const int64_t iaddr = p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col;
+            out += br * Cin[iaddr];
+          }
+          if (row == col) out += gam;
+        }
+        Cg[caddr] = out;
+      }
+}
+
+// Tile shapes (BM, BN, BKT, WM, WN).
+template <typename T, bool CPLX> struct Shape;
+template <> struct Shape<double, true>  { static constexpr int BM = 128, BN = 64, BKT = 8,  WM = 4, WN = 2; };
+template <> struct Shape<double, false> { static constexpr int BM = 128, BN = 64, BKT = 16, WM = 4, WN = 2; };
+template <> struct Shape<float, true>   { static constexpr int BM = 128, BN = 64, BKT = 16, WM = 4, WN = 2; };
+template <> struct Shape<float, false>  { static constexpr int BM = 128, BN = 64, BKT = 16, WM = 4, WN = 2; };
+
+template <typename T, bool CPLX, bool AK, bool BK>
+int launch4(const GemmDesc& d, hipStream_t s) {
+  typedef Shape<T, CPLX> S;
+  Params p;
+  p.M = d.M; p.N = d.N; p.K = d.K;
+  p.A = d.A; p.lda = d.lda; p.B = d.B; p.ldb = d.ldb;
+  p.C = d.C; p.ldc = d.ldc; p.Cin = d.Cin; p.ldcin = d.ldcin;
+  p.alpha_re = d.alpha_re; p.alpha_im = d.alpha_im;
+  p.beta_re = d.beta_re; p.beta_im = d.beta_im; p.gamma = d.gamma;
+  p.conj_a = d.conj_a; p.conj_b = d.conj_b; p.c_trans = d.c_trans; p.cin_trans = d.cin_trans;
+  p.tiles_m = int((d.M + S::BM - 1) / S::BM);
+  p.tiles_n = int((d.N + S::BN - 1) / S::BN);
+  const int64_t tiles = int64_t(p.tiles_m) * p.tiles_n;
+  if (tiles <= 0) return TC_OK;
+  if (tiles > (int64_t(1) << 31) - 1) { set_error("product too large"); return TC_ERR_UNSUPPORTED; }
+  const bool exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
+  const dim3 grid{unsigned(tiles), 1u, 1u}, block{256u, 1u, 1u};
+  ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
+  if (exact)
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN>),
+                       grid, block, 0, s, p);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, true, S::BM, S::BN, S::BKT, S::WM, S::WN>),
+                       grid, block, 0, s, p);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+template <typename T, bool CPLX>
+int launch2(const GemmDesc& d, hipStream_t s) {
+  if (d.a_kmaj && d.b_kmaj) return launch4<T, CPLX, true, true>(d, s);
+  if (d.a_kmaj && !d.b_kmaj) return launch4<T, CPLX, true, false>(d, s);
+  if (!d.a_kmaj && d.b_kmaj) return launch4<T, CPLX, false, true>(d, s);
+  return launch4<T, CPLX, false, false>(d, s);
+}
+
+}  // namespace
+
+int gemm_f64(const GemmDesc& d, hipStream_t s) {
+  if (d.M == 0 || d.N == 0) return TC_OK;
+  return d.complex ? launch2<double, true>(d, s) : launch2<double, false>(d, s);
+}
+
+int gemm_f32(const GemmDesc& d, hipStream_t s) {
+  if (d.M == 0 || d.N == 0) return TC_OK;
+  return d.complex ? launch2<float, true>(d, s) : launch2<float, false>(d, s);
+}
+
+}  // namespace tcm

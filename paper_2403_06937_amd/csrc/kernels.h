@@ -1,0 +1,60 @@
+// Host launchers of the HBM-bound and latency-bound kernels of libtcm.
+#pragma once
+#include "common.h"
+
+namespace tcm {
+
+// a1: dense Eq. (4) into H (N x N, ldh).
+int launch_ham_fill(const ModelArgs& m, double* H, int64_t ldh, hipStream_t s);
+
+// out = a * X + b * I  (real N x N).
+int launch_axpb_identity(const double* X, int64_t ldx, double a, double b,
+                         double* out, int64_t ldo, int64_t N, hipStream_t s);
+
+// U = ph * (Cm - i Sm) (complex from two real N x N), ph = (ph_re, ph_im).
+int launch_assemble_cs(const double* Cm, const double* Sm, int64_t ld, double ph_re,
+                       double ph_im, c128* U, int64_t ldu, int64_t N, hipStream_t s);
+
+// U <- (U + U^T) / 2 in place (complex, square).
+int launch_symmetrize(c128* U, int64_t ldu, int64_t N, hipStream_t s);
+
+// Copies with type conversion; ld in elements.
+int launch_copy_c128_to_c64(const c128* src, int64_t lds, c64* dst, int64_t ldd,
+                            int64_t rows, int64_t cols, hipStream_t s);
+int launch_copy_c64_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd,
+                            int64_t rows, int64_t cols, hipStream_t s);
+
+// Rotating frame: U~[i][j] = e^{+i w_c k_i dt} U[i][j] minus the identity (D = U~ - I)
+// written as c128 (row phase with the excitation number k_i of row i).
+int launch_rotating_d(const ModelArgs& m, const c128* U, int64_t ldu, double dt,
+                      c128* D, int64_t ldd, hipStream_t s);
+int launch_rotating_d_c64(const ModelArgs& m, const c128* U, int64_t ldu, double dt,
+                          c64* D, int64_t ldd, hipStream_t s);
+
+// Element phase rho[i][j] *= e^{-i w_c (k_i - k_j) t} (t = elapsed time), for the
+// FP64 master (c128) or the FP32 master (c64).
+int launch_frame_phase_c128(const ModelArgs& m, c128* rho, int64_t ld, double t, hipStream_t s);
+int launch_frame_phase_c64(const ModelArgs& m, c64* rho, int64_t ld, double t, hipStream_t s);
+
+// Per-step readout of the diagonal: pop[r] = sum_s |l(s)| Re rho_ss and, if
+// pdist != NULL, pdist[r*(c+1) + m] = sum_{photon(s) = m} Re rho_ss.
+int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,
+                        double* pdist, hipStream_t s);
+int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
+                       double* pdist, hipStream_t s);
+
+// Hermitise and divide by Re Tr rho, in FP64.  scratch: device double[2]
+// (trace, non-finite flag).  For c64 storage the arithmetic is FP64 too.
+int launch_renorm_c128(c128* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s);
+int launch_renorm_c64(c64* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s);
+
+// tc_observables: partials buffer of observables_partials_size() doubles.
+size_t observables_partials_count(int64_t N);
+int launch_observables(const ModelArgs& m, const void* rho, int dtype, int64_t ld,
+                       double* partials, double* scalars, double* atom_pop,
+                       double* photon_dist, double* exc_dist, hipStream_t s);
+
+// bfloat16 hi/lo split of binary32 values.
+int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
+
+}  // namespace tcm

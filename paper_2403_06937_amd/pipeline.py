@@ -1,0 +1,74 @@
+"""The usual call sequence of the C ABI on torch device tensors.
+
+  build H (tc_build_hamiltonian) -> bounds (tc_spectral_bounds) -> U (tc_expm)
+  -> time steps (tc_evolve) -> readout (tc_observables)
+
+Each function only allocates device tensors and calls the library; no
+arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (Model, TC_C128, TC_C64, TC_EXPM_SS_TAYLOR, TC_FRAME_LAB, TC_GEMM_F64,
+               make_instance, make_opts, tc_build_hamiltonian, tc_evolve, tc_expm,
+               tc_observables, tc_spectral_bounds)
+
+
+def model_of(inst) -> Model:
+    """Model from an object with n, c, g, omega_a, omega_c attributes."""
+    return Model(int(inst.n), int(inst.c), list(map(float, inst.g)),
+                 list(map(float, inst.omega_a)), float(getattr(inst, "omega_c", 1.0)))
+
+
+def hamiltonian(model: Model, device="cuda") -> torch.Tensor:
+    N = model.N
+    H = torch.empty((N, N), dtype=torch.float64, device=device)
+    tc_build_hamiltonian(model, H)
+    return H
+
+
+def propagator(model: Model, dt: float, method: int = TC_EXPM_SS_TAYLOR, device="cuda",
+               H: torch.Tensor = None):
+    """(H, U) with U = exp(-i H dt) formed on the device."""
+    if H is None:
+        H = hamiltonian(model, device)
+    lo, hi = tc_spectral_bounds(model)
+    U = torch.empty((model.N, model.N), dtype=torch.complex128, device=device)
+    tc_expm(H, dt, lo, hi, U, method)
+    return H, U
+
+
+def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: float,
+           gemm_mode: int = TC_GEMM_F64, frame: int = TC_FRAME_LAB, renorm_every: int = 0,
+           record_every: int = 1, checkpoint_every: int = 0, record_photons: bool = False,
+           ws=None):
+    """Steps rho (device, complex128 or complex64) in place; returns the records
+    (pop [R], photon distribution [R, c+1] or None, checkpoints or None)."""
+    rho_dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
+    R = steps // record_every + 1 if record_every else 0
+    pop = torch.zeros(R, dtype=torch.float64, device=rho.device) if R else None
+    pd = (torch.zeros((R, model.c + 1), dtype=torch.float64, device=rho.device)
+          if (R and record_photons) else None)
+    ck = None
+    if checkpoint_every:
+        ck = torch.empty((steps // checkpoint_every + 1, model.N, model.N), dtype=rho.dtype,
+                         device=rho.device)
+    opts = make_opts(steps, dt, gemm_mode, rho_dtype, frame, renorm_every,
+                     record_every if record_every else 0, checkpoint_every)
+    inst = make_instance(model, U, rho, pop, pd, ck)
+    tc_evolve([inst], opts, ws=ws, device=rho.device)
+    return pop, pd, ck
+
+
+def observables(model: Model, rho: torch.Tensor) -> dict:
+    s = torch.zeros(8, dtype=torch.float64, device=rho.device)
+    ap = torch.zeros(model.n, dtype=torch.float64, device=rho.device)
+    pd = torch.zeros(model.c + 1, dtype=torch.float64, device=rho.device)
+    ed = torch.zeros(model.n + model.c + 1, dtype=torch.float64, device=rho.device)
+    tc_observables(model, rho, s, ap, pd, ed)
+    v = s.cpu().numpy()
+    return {"trace_re": v[0], "trace_im": v[1], "purity": v[2], "herm_err": v[3],
+            "excitation_total": v[4], "photon_mean": v[5], "excitation_mean": v[6],
+            "nonfinite": v[7], "atom_pop": ap.cpu().numpy(), "photon_dist": pd.cpu().numpy(),
+            "exc_dist": ed.cpu().numpy()}

@@ -1,0 +1,133 @@
+"""Boundary tests that need no GPU: the C-ABI library loads, exports every
+entry point include/tcm.h declares, and its host-only calls validate
+arguments before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import tcm_inputs as ti
+from oracle import model as omodel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+tcm = pytest.importorskip("paper_2403_06937_amd")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tcm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(tc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tcm.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(tcm.EXPORTED)
+
+
+def test_version_and_dim():
+    assert tcm.tc_version() == 100
+    assert tcm.tc_dim(3, 3) == 32
+    assert tcm.tc_dim(11, 5) == 12288
+    assert tcm.tc_dim(1, 0) == 2
+
+
+@pytest.mark.parametrize("n,c", [(0, 3), (-1, 1), (25, 1), (3, -1), (24, 20)])
+def test_dim_rejects(n, c):
+    with pytest.raises(tcm.TcmError) as e:
+        tcm.tc_dim(n, c)
+    assert e.value.code == tcm.TC_ERR_INVALID_ARGUMENT
+    assert "invalid argument" in str(e.value)
+
+
+@pytest.mark.parametrize("n,c,seed", [(1, 3, 0), (3, 3, 1), (5, 2, 2), (2, 0, 3)])
+def test_spectral_bounds_contain_spectrum(n, c, seed):
+    """Gershgorin interval from the host call contains every eigenvalue of the
+    oracle's H and equals the row-wise centre -/+ radius bounds."""
+    inst = ti.random_model(n, c, seed)
+    m = tcm.Model(n, c, inst.g, inst.omega_a)
+    lo, hi = tcm.tc_spectral_bounds(m)
+    H = omodel.hamiltonian(n, c, inst.g, inst.omega_a)
+    ev = np.linalg.eigvalsh(H)
+    assert lo <= ev.min() + 1e-12 and ev.max() <= hi + 1e-12
+    d = np.diagonal(H)
+    rad = np.sum(np.abs(H), axis=1) - np.abs(d)
+    assert abs(lo - np.min(d - rad)) < 1e-12 and abs(hi - np.max(d + rad)) < 1e-12
+
+
+def test_argument_errors_before_device_work():
+    L = tcm.lib()
+    m = tcm.Model(2, 1, [0.01, 0.02], [1.0, 1.0])
+    # NULL H
+    assert L.tc_build_hamiltonian(ctypes.byref(m.struct), None, 8, None) == tcm.TC_ERR_INVALID_ARGUMENT
+    # ld < N
+    assert L.tc_build_hamiltonian(ctypes.byref(m.struct), 0x1000, 4, None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert b"ldh" in L.tc_last_error()
+    # unknown expm method
+    sz = ctypes.c_size_t()
+    assert L.tc_expm_workspace_size(8, 7, ctypes.byref(sz)) == tcm.TC_ERR_INVALID_ARGUMENT
+    # workspace too small
+    assert L.tc_expm_workspace_size(8, tcm.TC_EXPM_SS_TAYLOR, ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    rc = L.tc_expm(0x1000, 8, 8, 0.1, 0.0, 1.0, tcm.TC_EXPM_SS_TAYLOR, 0x2000, 8, 0x3000,
+                   sz.value - 1, None)
+    assert rc == tcm.TC_ERR_WORKSPACE
+    # non-finite dt, inverted bounds
+    assert L.tc_expm(0x1000, 8, 8, float("nan"), 0.0, 1.0, 0, 0x2000, 8, 0x3000, sz.value,
+                     None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert L.tc_expm(0x1000, 8, 8, 0.1, 1.0, 0.0, 0, 0x2000, 8, 0x3000, sz.value,
+                     None) == tcm.TC_ERR_INVALID_ARGUMENT
+
+
+def test_evolve_argument_errors():
+    m = tcm.Model(2, 1, [0.01, 0.02], [1.0, 1.0])
+    N = m.N
+
+    class Fake:
+        def __init__(self, p, ld):
+            self.p, self.ld = p, ld
+
+        def data_ptr(self):
+            return self.p
+
+        def stride(self, i):
+            return self.ld
+
+    U, rho = Fake(0x1000, N), Fake(0x2000, N)
+    inst = tcm.make_instance(m, U, rho)
+    for bad in [dict(steps=-1), dict(gemm_mode=9), dict(rho_dtype=7), dict(frame=3),
+                dict(renorm_every=-2), dict(record_every=-1)]:
+        kw = dict(steps=10, dt=0.1)
+        kw.update(bad)
+        with pytest.raises(tcm.TcmError) as e:
+            tcm.tc_evolve_workspace_size([inst], tcm.make_opts(**kw))
+        assert e.value.code == tcm.TC_ERR_INVALID_ARGUMENT
+    # records requested with record_every = 0
+    inst2 = tcm.make_instance(m, U, rho, pop_out=Fake(0x3000, 1))
+    with pytest.raises(tcm.TcmError):
+        tcm.tc_evolve_workspace_size([inst2], tcm.make_opts(10, 0.1, record_every=0))
+    # wrong N
+    inst3 = tcm.make_instance(m, U, rho)
+    inst3.N = N + 1
+    with pytest.raises(tcm.TcmError):
+        tcm.tc_evolve_workspace_size([inst3], tcm.make_opts(10, 0.1))
+    # workspace too small -> TC_ERR_WORKSPACE, nothing launched
+    need = tcm.tc_evolve_workspace_size([inst], tcm.make_opts(10, 0.1))
+    arr = (tcm.tc_instance * 1)(inst)
+    opts = tcm.make_opts(10, 0.1)
+    rc = tcm.lib().tc_evolve(arr, 1, ctypes.byref(opts), 0x4000, need - 1, None)
+    assert rc == tcm.TC_ERR_WORKSPACE
+
+
+def test_workspace_sizes_scale():
+    a = tcm.tc_expm_workspace_size(1024)
+    b = tcm.tc_expm_workspace_size(2048)
+    assert 3.9 < b / a < 4.1
+    assert tcm.tc_gemm_workspace_size(64, 64, 64, tcm.TC_GEMM_F64) == 0
+    assert tcm.tc_gemm_workspace_size(64, 64, 64, tcm.TC_GEMM_SPLIT_BF16) > 0
