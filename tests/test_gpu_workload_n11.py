@@ -1,0 +1,107 @@
+"""Full-size parity at N = 12288 (n = 11 atoms, photon cutoff 5, 2 photons x
+Haar product state, dt = 0.05, renormalised every 20 steps) in the launch
+configuration bench.py times.  The oracle is the exact excitation-sector
+evolution of the pure state; every entry of the final rho is compared."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import tcm_inputs as ti
+from oracle import evolve as oev
+from oracle import model as omodel
+
+pytestmark = pytest.mark.gpu
+
+tcm = pytest.importorskip("paper_2403_06937_amd")
+from paper_2403_06937_amd import pipeline  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = ti.get("n11")
+    inst = w.instances[0]
+    model = pipeline.model_of(inst)
+    _, U = pipeline.propagator(model, w.dt)
+    t0 = time.time()
+    P = oev.SectorPropagator(inst.n, inst.c, inst.g, inst.omega_a)
+    print(f"oracle sector eigendecompositions {time.time() - t0:.1f}s", flush=True)
+    O = sum(omodel.atom_excitation_diag(inst.n, inst.c, i) for i in range(inst.n))
+    return w, inst, model, U, P, O
+
+
+def max_entry_error(rho, psi, block=1024):
+    err = 0.0
+    for r0 in range(0, psi.size, block):
+        err = max(err, float(np.max(np.abs(rho[r0:r0 + block] - np.outer(psi[r0:r0 + block], psi.conj())))))
+    return err
+
+
+def test_split_bf16_full_run(setup):
+    """All 200 steps in split-BF16 (rotating frame): max-entry and population
+    error against the FP64 oracle at most 1e-5."""
+    w, inst, model, U, P, O = setup
+    rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
+    t0 = time.time()
+    pop, _, _ = pipeline.evolve(model, U, rho, w.steps, w.dt, tcm.TC_GEMM_SPLIT_BF16,
+                                tcm.TC_FRAME_ROTATING, w.renorm_every, 1)
+    torch.cuda.synchronize()
+    print(f"gpu split-bf16 {w.steps} steps {time.time() - t0:.2f}s", flush=True)
+    psiT = P.psi(inst.psi0, w.steps * w.dt)
+    err = max_entry_error(rho.cpu().numpy().astype(np.complex128), psiT)
+    popn = pop.cpu().numpy()
+    perr = max(abs(popn[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * w.dt)) ** 2)))
+               for s in range(0, w.steps + 1, 10))
+    print(f"N=12288 split-bf16: max-entry error {err:.3e}, population error {perr:.3e}", flush=True)
+    assert err <= 1e-5
+    assert perr <= 1e-5
+
+
+def test_fp32_partial_run(setup):
+    w, inst, model, U, P, O = setup
+    steps = 40
+    rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
+    pipeline.evolve(model, U, rho, steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING,
+                    w.renorm_every, 1)
+    err = max_entry_error(rho.cpu().numpy().astype(np.complex128), P.psi(inst.psi0, steps * w.dt))
+    print(f"N=12288 complex-fp32 ({steps} steps): max-entry error {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_fp64_partial_run(setup):
+    """FP64 over 20 steps (one renormalisation): every entry within 1e-10."""
+    w, inst, model, U, P, O = setup
+    steps = 20
+    rho = torch.from_numpy(inst.rho0()).to("cuda")
+    t0 = time.time()
+    pop, _, _ = pipeline.evolve(model, U, rho, steps, w.dt, tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB,
+                                w.renorm_every, 1)
+    torch.cuda.synchronize()
+    print(f"gpu fp64 {steps} steps {time.time() - t0:.2f}s", flush=True)
+    err = max_entry_error(rho.cpu().numpy(), P.psi(inst.psi0, steps * w.dt))
+    popn = pop.cpu().numpy()
+    perr = max(abs(popn[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * w.dt)) ** 2)))
+               for s in range(steps + 1))
+    print(f"N=12288 fp64: max-entry error {err:.3e}, population error {perr:.3e}", flush=True)
+    assert err <= 1e-10 and perr <= 1e-10
+
+
+def test_propagator_sampled_entries(setup):
+    """U = exp(-i H dt) at N = 12288 against the oracle's sector eigendecomposition
+    on 64 sampled columns, plus exact zeros across sectors."""
+    w, inst, model, U, P, O = setup
+    rng = np.random.default_rng(0)
+    cols = rng.choice(inst.N, 64, replace=False)
+    Ug = U[:, torch.from_numpy(cols).to("cuda")].cpu().numpy()
+    err = 0.0
+    for j, col in enumerate(cols):
+        e = np.zeros(inst.N, dtype=complex)
+        e[col] = 1
+        err = max(err, float(np.max(np.abs(Ug[:, j] - P.psi(e, w.dt)))))
+    k = omodel.total_excitation_diag(inst.n, inst.c)
+    assert np.all(Ug[k[:, None] != k[cols][None, :]] == 0)
+    print(f"N=12288 U sampled-column error {err:.3e}", flush=True)
+    assert err < 1e-13
