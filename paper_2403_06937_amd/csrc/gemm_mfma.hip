@@ -23,6 +23,8 @@
 #include "gemm_mfma.h"
 #include "profile.h"
 
+#include <cstdlib>
+
 namespace tcm {
 namespace {
 
@@ -72,6 +74,14 @@ struct Params {
 
 constexpr int GROUP_M = 8;
 
+// Default tile variant per element type for the step / exponential layout,
+// chosen by timing every variant at N = 12288 on gfx950:
+//   complex FP64: 64x64 tiles, 4 waves (285 ms per product; 128x64: 438 ms)
+//   real FP64:    128x128 tiles, 8 waves (U formation 1.07 s; 128x64: 1.42 s)
+//   complex FP32: 128x128 tiles, 8 waves (112 ms; 128x64: 118 ms)
+template <typename T, bool CPLX> struct DefaultVariant { static constexpr int value = 1; };
+template <> struct DefaultVariant<double, true> { static constexpr int value = 2; };
+
 // Tile coordinates of this workgroup (XCD-contiguous, grouped ordering).
 __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
   const int total = tiles_m * tiles_n;
@@ -89,23 +99,31 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
 
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
           int BM, int BN, int BKT, int WM, int WN>
-__global__ void __launch_bounds__(256)
-gemm_kernel(Params p) {
+__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
+gemm_kernel(const Params p) {
   typedef typename elem<T, CPLX>::type E;
   typedef typename acc_t<T>::type A4;
   constexpr int WGN = BN / (16 * WN);
   constexpr int WGM = BM / (16 * WM);
-  static_assert(WGM * WGN == 4, "4 waves per workgroup");
+  constexpr int NT = 64 * WGM * WGN;          // threads per workgroup
   static_assert(BKT % 4 == 0, "K tile is a multiple of the MFMA depth");
   constexpr int PADE = 16 / sizeof(E) > 0 ? 16 / sizeof(E) : 1;  // 16 bytes of padding
   constexpr int LDA_S = BM + PADE;
   constexpr int LDB_S = BN + PADE;
-  constexpr int A_PT = BKT * BM / 256;   // staged elements per thread
-  constexpr int B_PT = BKT * BN / 256;
-  static_assert(BKT * BM % 256 == 0 && BKT * BN % 256 == 0, "tile split");
+  constexpr int A_PT = BKT * BM / NT;          // staged elements per thread
+  constexpr int B_PT = BKT * BN / NT;
+  static_assert(BKT * BM % NT == 0 && BKT * BN % NT == 0, "tile split");
+  // a thread's staged elements share one row (K-major) or one column of the tile
+  static_assert(AK ? NT % BM == 0 : NT % BKT == 0, "A staging pattern");
+  static_assert(BK ? NT % BN == 0 : NT % BKT == 0, "B staging pattern");
 
   __shared__ E sA[2][BKT][LDA_S];
   __shared__ E sB[2][BKT][LDB_S];
+
+  // kernel arguments into registers once
+  const int64_t M = p.M, N = p.N, K = p.K;
+  const int64_t lda = p.lda, ldb = p.ldb;
+  const bool cja = p.conj_a != 0, cjb = p.conj_b != 0;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -115,9 +133,25 @@ gemm_kernel(Params p) {
   tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
-  const E* __restrict__ Ag = static_cast<const E*>(p.A);
-  const E* __restrict__ Bg = static_cast<const E*>(p.B);
-  const bool cja = p.conj_a, cjb = p.conj_b;
+  // Staging pattern: element j of this thread sits at (ka + j*dka, ma + j*dma)
+  // of the A tile and (kb + j*dkb, nb + j*dnb) of the B tile.
+  const int ka = AK ? tid / BM : tid % BKT;
+  const int ma = AK ? tid % BM : tid / BKT;
+  constexpr int dka = AK ? NT / BM : 0;
+  constexpr int dma = AK ? 0 : NT / BKT;
+  const int kb = BK ? tid / BN : tid % BKT;
+  const int nb = BK ? tid % BN : tid / BKT;
+  constexpr int dkb = BK ? NT / BN : 0;
+  constexpr int dnb = BK ? 0 : NT / BKT;
+  // global offsets of element 0 at k0 = 0, strides per j and per K tile
+  const E* __restrict__ pa = static_cast<const E*>(p.A) +
+      (AK ? int64_t(ka) * lda + (m0 + ma) : (m0 + ma) * lda + ka);
+  const E* __restrict__ pb = static_cast<const E*>(p.B) +
+      (BK ? int64_t(kb) * ldb + (n0 + nb) : (n0 + nb) * ldb + kb);
+  const int64_t sja = AK ? int64_t(dka) * lda : int64_t(dma) * lda;
+  const int64_t sjb = BK ? int64_t(dkb) * ldb : int64_t(dnb) * ldb;
+  const int64_t ska = AK ? int64_t(BKT) * lda : BKT;
+  const int64_t skb = BK ? int64_t(BKT) * ldb : BKT;
 
   A4 acc_re[WM][WN], acc_im[WM][WN];
 #pragma unroll
@@ -129,47 +163,34 @@ gemm_kernel(Params p) {
     }
 
   E ra[A_PT], rb[B_PT];
+  const int64_t ktiles = (K + BKT - 1) / BKT;
 
-  auto load_tiles = [&](int64_t k0) {
+  auto load_tiles = [&](int64_t kt) {
+    const E* qa = pa + kt * ska;
+    const E* qb = pb + kt * skb;
+    const int64_t k0 = kt * BKT;
 #pragma unroll
     for (int j = 0; j < A_PT; ++j) {
-      const int e = tid + 256 * j;
-      int kk, mm;
-      if (AK) { kk = e / BM; mm = e % BM; } else { kk = e % BKT; mm = e / BKT; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      const int64_t addr = AK ? gk * p.lda + gm : gm * p.lda + gk;
-      if (CHECKED && (gm >= p.M || gk >= p.K)) ra[j] = elem<T, CPLX>::zero();
-      else ra[j] = elem<T, CPLX>::cj(Ag[addr], cja);
+      if (CHECKED && (m0 + ma + j * dma >= M || k0 + ka + j * dka >= K))
+        ra[j] = elem<T, CPLX>::zero();
+      else
+        ra[j] = elem<T, CPLX>::cj(qa[j * sja], cja);
     }
 #pragma unroll
     for (int j = 0; j < B_PT; ++j) {
-      const int e = tid + 256 * j;
-      int kk, nn;
-      if (BK) { kk = e / BN; nn = e % BN; } else { kk = e % BKT; nn = e / BKT; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      const int64_t addr = BK ? gk * p.ldb + gn : gn * p.ldb + gk;
-      if (CHECKED && (gn >= p.N || gk >= p.K)) rb[j] = elem<T, CPLX>::zero();
-      else rb[j] = elem<T, CPLX>::cj(Bg[addr], cjb);
+      if (CHECKED && (n0 + nb + j * dnb >= N || k0 + kb + j * dkb >= K))
+        rb[j] = elem<T, CPLX>::zero();
+      else
+        rb[j] = elem<T, CPLX>::cj(qb[j * sjb], cjb);
     }
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < A_PT; ++j) {
-      const int e = tid + 256 * j;
-      int kk, mm;
-      if (AK) { kk = e / BM; mm = e % BM; } else { kk = e % BKT; mm = e / BKT; }
-      sA[buf][kk][mm] = ra[j];
-    }
+    for (int j = 0; j < A_PT; ++j) sA[buf][ka + j * dka][ma + j * dma] = ra[j];
 #pragma unroll
-    for (int j = 0; j < B_PT; ++j) {
-      const int e = tid + 256 * j;
-      int kk, nn;
-      if (BK) { kk = e / BN; nn = e % BN; } else { kk = e % BKT; nn = e / BKT; }
-      sB[buf][kk][nn] = rb[j];
-    }
+    for (int j = 0; j < B_PT; ++j) sB[buf][kb + j * dkb][nb + j * dnb] = rb[j];
   };
 
-  const int64_t ktiles = (p.K + BKT - 1) / BKT;
   if (ktiles > 0) {
     load_tiles(0);
     store_tiles(0);
@@ -180,7 +201,7 @@ gemm_kernel(Params p) {
   const int lcol = lane & 15;   // m / n offset within the 16-wide block
   for (int64_t kt = 0; kt < ktiles; ++kt) {
     const int buf = int(kt & 1);
-    if (kt + 1 < ktiles) load_tiles((kt + 1) * BKT);
+    if (kt + 1 < ktiles) load_tiles(kt + 1);
 #pragma unroll
     for (int k4 = 0; k4 < BKT / 4; ++k4) {
       E a[WM], b[WN];
@@ -209,6 +230,8 @@ gemm_kernel(Params p) {
   // Epilogue: C = alpha * acc + beta * Cin + gamma * [m == n]
   E* __restrict__ Cg = static_cast<E*>(p.C);
   const E* __restrict__ Cin = static_cast<const E*>(p.Cin);
+  const int64_t ldc = p.ldc, ldcin = p.ldcin;
+  const bool ctr = p.c_trans != 0, citr = p.cin_trans != 0;
   const T ar = T(p.alpha_re), ai = T(p.alpha_im), br = T(p.beta_re), bi = T(p.beta_im);
   const T gam = T(p.gamma);
   const bool use_beta = (Cin != nullptr) && (p.beta_re != 0.0 || p.beta_im != 0.0);
@@ -222,42 +245,66 @@ gemm_kernel(Params p) {
         const int64_t row = m0 + (wm * WM + i) * 16 +
                             (sizeof(T) == 8 ? lrow + 4 * r : 4 * lrow + r);
         const int64_t col = n0 + (wn * WN + j) * 16 + lcol;
-        if (CHECKED && (row >= p.M || col >= p.N)) continue;
-        const int64_t caddr = p.c_trans ? col * p.ldc + row : row * p.ldc + col;
+        if (CHECKED && (row >= M || col >= N)) continue;
+        const int64_t caddr = ctr ? col * ldc + row : row * ldc + col;
         E out;
         if constexpr (CPLX) {
           const T xr = acc_re[i][j][r], xi = acc_im[i][j][r];
           out.re = ar * xr - ai * xi;
           out.im = ar * xi + ai * xr;
           if (use_beta) {
-            const int64_t iaddr = p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col;
-            const E y = Cin[iaddr];
+            const E y = Cin[citr ? col * ldcin + row : row * ldcin + col];
             out.re += br * y.re - bi * y.im;
             out.im += br * y.im + bi * y.re;
           }
           if (row == col) out.re += gam;
         } else {
           out = ar * acc_re[i][j][r];
-          if (use_beta) {
-            const int64_t iaddr = p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col;
-            out += br * Cin[iaddr];
-          }
+          if (use_beta) out += br * Cin[citr ? col * ldcin + row : row * ldcin + col];
           if (row == col) out += gam;
         }
         Cg[caddr] = out;
       }
 }
 
-// Tile shapes (BM, BN, BKT, WM, WN).
-template <typename T, bool CPLX> struct Shape;
-template <> struct Shape<double, true>  { static constexpr int BM = 128, BN = 64, BKT = 8,  WM = 4, WN = 2; };
-template <> struct Shape<double, false> { static constexpr int BM = 128, BN = 64, BKT = 16, WM = 4, WN = 2; };
-template <> struct Shape<float, true>   { static constexpr int BM = 128, BN = 64, BKT = 16, WM = 4, WN = 2; };
-template <> struct Shape<float, false>  { static constexpr int BM = 128, BN = 64, BKT = 16, WM = 4, WN = 2; };
+// Tile shapes (BM, BN, BKT, WM, WN); the wave count is (BM/16WM)(BN/16WN).
+struct ShapeDesc { int BM, BN, BKT, WM, WN; };
 
-template <typename T, bool CPLX, bool AK, bool BK>
-int launch4(const GemmDesc& d, hipStream_t s) {
-  typedef Shape<T, CPLX> S;
+template <int BM_, int BN_, int BKT_, int WM_, int WN_> struct Shp {
+  static constexpr int BM = BM_, BN = BN_, BKT = BKT_, WM = WM_, WN = WN_;
+  static constexpr int NT = 64 * (BM / (16 * WM)) * (BN / (16 * WN));
+};
+
+// Variant lists per element type; variant 0 is the default for every layout,
+// the others serve the step and exponential layout (A row-major, B row-major).
+template <typename T, bool CPLX> struct Variants;
+template <> struct Variants<double, true> {
+  typedef Shp<128, 64, 8, 4, 2> V0;
+  typedef Shp<128, 128, 8, 4, 2> V1;
+  typedef Shp<64, 64, 16, 2, 2> V2;
+  typedef Shp<128, 128, 8, 2, 4> V3;
+};
+template <> struct Variants<double, false> {
+  typedef Shp<128, 64, 16, 4, 2> V0;
+  typedef Shp<128, 128, 16, 4, 2> V1;
+  typedef Shp<64, 64, 16, 2, 2> V2;
+  typedef Shp<128, 128, 16, 2, 4> V3;
+};
+template <> struct Variants<float, true> {
+  typedef Shp<128, 64, 16, 4, 2> V0;
+  typedef Shp<128, 128, 16, 4, 2> V1;
+  typedef Shp<64, 64, 16, 2, 2> V2;
+  typedef Shp<128, 128, 16, 2, 4> V3;
+};
+template <> struct Variants<float, false> {
+  typedef Shp<128, 64, 16, 4, 2> V0;
+  typedef Shp<128, 128, 16, 4, 2> V1;
+  typedef Shp<64, 64, 16, 2, 2> V2;
+  typedef Shp<128, 128, 16, 2, 4> V3;
+};
+
+template <typename T, bool CPLX, bool AK, bool BK, typename S>
+int launch_shape(const GemmDesc& d, hipStream_t s) {
   Params p;
   p.M = d.M; p.N = d.N; p.K = d.K;
   p.A = d.A; p.lda = d.lda; p.B = d.B; p.ldb = d.ldb;
@@ -271,7 +318,7 @@ int launch4(const GemmDesc& d, hipStream_t s) {
   if (tiles <= 0) return TC_OK;
   if (tiles > (int64_t(1) << 31) - 1) { set_error("product too large"); return TC_ERR_UNSUPPORTED; }
   const bool exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
-  const dim3 grid{unsigned(tiles), 1u, 1u}, block{256u, 1u, 1u};
+  const dim3 grid{unsigned(tiles), 1u, 1u}, block{unsigned(S::NT), 1u, 1u};
   ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
   if (exact)
     hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN>),
@@ -283,12 +330,28 @@ int launch4(const GemmDesc& d, hipStream_t s) {
   return TC_OK;
 }
 
+int variant_for(int default_variant) {
+  static const int env = [] {
+    const char* v = getenv("TC_GEMM_VARIANT");
+    return v ? atoi(v) : -1;
+  }();
+  return env >= 0 ? env : default_variant;
+}
+
 template <typename T, bool CPLX>
 int launch2(const GemmDesc& d, hipStream_t s) {
-  if (d.a_kmaj && d.b_kmaj) return launch4<T, CPLX, true, true>(d, s);
-  if (d.a_kmaj && !d.b_kmaj) return launch4<T, CPLX, true, false>(d, s);
-  if (!d.a_kmaj && d.b_kmaj) return launch4<T, CPLX, false, true>(d, s);
-  return launch4<T, CPLX, false, false>(d, s);
+  typedef Variants<T, CPLX> V;
+  if (!d.a_kmaj && d.b_kmaj) {
+    switch (variant_for(DefaultVariant<T, CPLX>::value)) {
+      case 1: return launch_shape<T, CPLX, false, true, typename V::V1>(d, s);
+      case 2: return launch_shape<T, CPLX, false, true, typename V::V2>(d, s);
+      case 3: return launch_shape<T, CPLX, false, true, typename V::V3>(d, s);
+      default: return launch_shape<T, CPLX, false, true, typename V::V0>(d, s);
+    }
+  }
+  if (d.a_kmaj && d.b_kmaj) return launch_shape<T, CPLX, true, true, typename V::V0>(d, s);
+  if (d.a_kmaj && !d.b_kmaj) return launch_shape<T, CPLX, true, false, typename V::V0>(d, s);
+  return launch_shape<T, CPLX, false, false, typename V::V0>(d, s);
 }
 
 }  // namespace
