@@ -364,6 +364,95 @@ __global__ void trace_im_kernel(const E* __restrict__ rho, int64_t ld, int64_t N
   if (threadIdx.x == 0) *out = t;
 }
 
+// ------------------------------------------------------------ adjoint helpers
+template <typename E>
+__global__ void excitation_op_kernel(ModelArgs m, E* __restrict__ O, int64_t ld) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= m.N) return;
+  const uint64_t mask = (uint64_t(1) << m.n) - 1;
+  typedef decltype(E().re) T;
+  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y) {
+    const T v = row == col ? T(popc64(uint64_t(row) & mask)) : T(0);
+    O[row * ld + col] = E{v, T(0)};
+  }
+}
+
+__global__ void accumulate_c64_kernel(const c64* __restrict__ T, int64_t ldt, c128* __restrict__ M,
+                                      int64_t ldm, int64_t N) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= N) return;
+  for (int64_t row = blockIdx.y; row < N; row += gridDim.y) {
+    const c64 t = T[row * ldt + col];
+    c128 v = M[row * ldm + col];
+    v.re += double(t.re);
+    v.im += double(t.im);
+    M[row * ldm + col] = v;
+  }
+}
+
+__global__ void minus_i_shifted_kernel(ModelArgs m, const double* __restrict__ H, int64_t ldh,
+                                       double mu, double scale, c128* __restrict__ out,
+                                       int64_t ldo) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= m.N) return;
+  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y) {
+    double h = H[row * ldh + col];
+    if (row == col) h -= m.omega_c * double(exc_number(row, m.n)) + mu;
+    out[row * ldo + col] = c128{0.0, -h * scale};
+  }
+}
+
+__global__ void scale_c128_kernel(c128* __restrict__ X, int64_t ld, double a, int64_t N) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= N) return;
+  for (int64_t row = blockIdx.y; row < N; row += gridDim.y) {
+    c128 v = X[row * ld + col];
+    X[row * ld + col] = c128{a * v.re, a * v.im};
+  }
+}
+
+__global__ void identity_c128_kernel(c128* __restrict__ X, int64_t ld, int64_t N) {
+  const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (col >= N) return;
+  for (int64_t row = blockIdx.y; row < N; row += gridDim.y)
+    X[row * ld + col] = c128{row == col ? 1.0 : 0.0, 0.0};
+}
+
+// One workgroup per parameter: blocks 0..n-1 give dL/dg_i, n..2n-1 dL/ddelta_i.
+__global__ void grad_trace_kernel(ModelArgs m, const c128* __restrict__ G, int64_t ld, double pr,
+                                  double pi, double dt, double* __restrict__ grad_g,
+                                  double* __restrict__ grad_delta) {
+  __shared__ double sh[TPB];
+  const int n = m.n;
+  const int p = blockIdx.x;
+  const int i = p % n;
+  const int64_t per = int64_t(1) << n;
+  const uint64_t bit = uint64_t(1) << (n - 1 - i);
+  double acc = 0.0;   // Im(ph * sum)
+  if (p < n) {
+    // pairs s = (mm, l) with bit set, mm < c; t = s + 2^n - bit
+    for (int64_t s = threadIdx.x; s < int64_t(m.c) * per; s += TPB) {
+      if (!(uint64_t(s) & bit)) continue;
+      const int64_t t = s + per - int64_t(bit);
+      const double w = sqrt(double((s >> n) + 1));
+      const c128 a = G[s * ld + t], b = G[t * ld + s];
+      const double zr = w * (a.re + b.re), zi = w * (a.im + b.im);
+      acc += pr * zi + pi * zr;
+    }
+  } else {
+    for (int64_t s = threadIdx.x; s < m.N; s += TPB) {
+      if (!(uint64_t(s) & bit)) continue;
+      const c128 a = G[s * ld + s];
+      acc += pr * a.im + pi * a.re;
+    }
+  }
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    if (p < n) grad_g[i] = 2.0 * dt * tot;
+    else grad_delta[i] = 2.0 * dt * tot;
+  }
+}
+
 // --------------------------------------------------------- bfloat16 split
 __device__ __forceinline__ uint16_t rne_bf16(float x) {
   const uint32_t b = __float_as_uint(x);
@@ -539,6 +628,59 @@ int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
   int64_t blocks = (count + TPB - 1) / TPB;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(split_bf16_kernel, dim3(unsigned(blocks)), dim3(TPB), 0, s, x, count, hi, lo);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_excitation_op_c128(const ModelArgs& m, c128* O, int64_t ld, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(excitation_op_kernel<c128>, grid2(m.N, m.N), dim3(TPB), 0, s, m, O, ld);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_excitation_op_c64(const ModelArgs& m, c64* O, int64_t ld, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(excitation_op_kernel<c64>, grid2(m.N, m.N), dim3(TPB), 0, s, m, O, ld);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_accumulate_c64(const c64* T, int64_t ldt, c128* M, int64_t ldm, int64_t N,
+                          hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(accumulate_c64_kernel, grid2(N, N), dim3(TPB), 0, s, T, ldt, M, ldm, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_minus_i_shifted(const ModelArgs& m, const double* H, int64_t ldh, double mu,
+                           double scale, c128* out, int64_t ldo, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  hipLaunchKernelGGL(minus_i_shifted_kernel, grid2(m.N, m.N), dim3(TPB), 0, s, m, H, ldh, mu,
+                     scale, out, ldo);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_scale_c128(c128* X, int64_t ld, double a, int64_t N, hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(scale_c128_kernel, grid2(N, N), dim3(TPB), 0, s, X, ld, a, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_identity_c128(c128* X, int64_t ld, int64_t N, hipStream_t s) {
+  if (N == 0) return TC_OK;
+  hipLaunchKernelGGL(identity_c128_kernel, grid2(N, N), dim3(TPB), 0, s, X, ld, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_grad_trace(const ModelArgs& m, const c128* G, int64_t ld, double ph_re, double ph_im,
+                      double dt, double* grad_g, double* grad_delta, hipStream_t s) {
+  hipLaunchKernelGGL(grad_trace_kernel, dim3(unsigned(2 * m.n)), dim3(TPB), 0, s, m, G, ld, ph_re,
+                     ph_im, dt, grad_g, grad_delta);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }

@@ -407,24 +407,4 @@ int tc_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, voi
   return launch_split_bf16(x, count, hi, lo, as_stream(stream));
 }
 
-int tc_evolve_backward_workspace_size(const tc_model* m, int64_t N, const tc_evolve_opts* o,
-                                      size_t* bytes) {
-  clear_error();
-  (void)m; (void)N; (void)o; (void)bytes;
-  set_error("tc_evolve_backward is not available in this build");
-  return TC_ERR_UNSUPPORTED;
-}
-
-int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc_c128* U,
-                       int64_t ldu, int64_t N, const tc_evolve_opts* o, const void* checkpoints,
-                       int32_t observable, double* loss_out, double* grad_g, double* grad_delta,
-                       void* ws, size_t ws_bytes, void* stream) {
-  clear_error();
-  (void)m; (void)H; (void)ldh; (void)U; (void)ldu; (void)N; (void)o; (void)checkpoints;
-  (void)observable; (void)loss_out; (void)grad_g; (void)grad_delta; (void)ws; (void)ws_bytes;
-  (void)stream;
-  set_error("tc_evolve_backward is not available in this build");
-  return TC_ERR_UNSUPPORTED;
-}
-
 }  // extern "C"

@@ -54,6 +54,28 @@ int launch_observables(const ModelArgs& m, const void* rho, int dtype, int64_t l
                        double* partials, double* scalars, double* atom_pop,
                        double* photon_dist, double* exc_dist, hipStream_t s);
 
+// ---- adjoint helpers
+// O = diag(sum_i s_i^+ s_i^-) written densely (zeros off the diagonal).
+int launch_excitation_op_c128(const ModelArgs& m, c128* O, int64_t ld, hipStream_t s);
+int launch_excitation_op_c64(const ModelArgs& m, c64* O, int64_t ld, hipStream_t s);
+// M += T (complex64 into complex128).
+int launch_accumulate_c64(const c64* T, int64_t ldt, c128* M, int64_t ldm, int64_t N,
+                          hipStream_t s);
+// out = -i (H - w_c N_exc - mu I) * scale  (complex128 from real FP64): the
+// rotating-frame generator H' = H - w_c N_exc, shifted by mu.
+int launch_minus_i_shifted(const ModelArgs& m, const double* H, int64_t ldh, double mu,
+                           double scale, c128* out, int64_t ldo, hipStream_t s);
+// X *= a (complex128, in place).
+int launch_scale_c128(c128* X, int64_t ld, double a, int64_t N, hipStream_t s);
+// X = I (complex128).
+int launch_identity_c128(c128* X, int64_t ld, int64_t N, hipStream_t s);
+// Parameter gradients from G (scaled by the complex factor ph):
+//   grad_g[i]     = 2 dt Im( ph sum_{s,t} sqrt(m+1) (G_st + G_ts) )   over the (s, t)
+//                   pairs coupled by g_i (s = (m, l) with l_i = 1, t = (m+1, l - e_i))
+//   grad_delta[i] = 2 dt Im( ph sum_{s: l_i = 1} G_ss )
+int launch_grad_trace(const ModelArgs& m, const c128* G, int64_t ld, double ph_re, double ph_im,
+                      double dt, double* grad_g, double* grad_delta, hipStream_t s);
+
 // bfloat16 hi/lo split of binary32 values.
 int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -1,0 +1,120 @@
+"""GPU adjoint gradient (tc_evolve_backward) against the oracle's
+Daleckii-Krein gradient and central finite differences, on a small case and
+on the n=8, c=8 (N=2304), 500-step workload with checkpoints every 50."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import tcm_inputs as ti
+from oracle import gradient as ograd
+from oracle import observables as oobs
+
+pytestmark = pytest.mark.gpu
+
+tcm = pytest.importorskip("paper_2403_06937_amd")
+from paper_2403_06937_amd import pipeline  # noqa: E402
+from paper_2403_06937_amd.autograd import TCMLoss  # noqa: E402
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    tcm.lib()
+
+
+def gpu_grad(inst, dt, steps, every, mode, rho_dtype):
+    m = pipeline.model_of(inst)
+    H, U = pipeline.propagator(m, dt)
+    rdt = tcm.TC_C128 if rho_dtype == torch.complex128 else tcm.TC_C64
+    rho = torch.from_numpy(inst.rho0()).to("cuda").to(rho_dtype)
+    # the forward runs in the rotating frame (its checkpoints are lab-frame states)
+    _, _, ck = pipeline.evolve(m, U, rho, steps, dt, mode, tcm.TC_FRAME_ROTATING, 0,
+                               steps if steps else 1, every)
+    opts = tcm.make_opts(steps, dt, mode, rdt, tcm.TC_FRAME_LAB, 0, 1, every)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gg = torch.zeros(inst.n, dtype=torch.float64, device="cuda")
+    gd = torch.zeros(inst.n, dtype=torch.float64, device="cuda")
+    tcm.tc_evolve_backward(m, H, U, opts, ck, loss, gg, gd)
+    torch.cuda.synchronize()
+    return float(loss.item()), gg.cpu().numpy(), gd.cpu().numpy()
+
+
+@pytest.mark.parametrize("state,steps,every", [("gaussian", 40, 7), ("excited", 40, 40), ("haar2", 13, 5)])
+def test_adjoint_fp64_small(state, steps, every):
+    inst = ti.random_model(3, 3, 61, delta_sigma=0.01, state=state)
+    dt = 0.5
+    L, gg, gd = gpu_grad(inst, dt, steps, every, tcm.TC_GEMM_F64, torch.complex128)
+    Lo, go, do = ograd.grad_daleckii_krein(inst.n, inst.c, inst.g, inst.omega_a - 1, inst.rho0(),
+                                           steps * dt)
+    scale = max(np.max(np.abs(go)), np.max(np.abs(do)))
+    assert abs(L - Lo) < 1e-12
+    assert np.max(np.abs(gg - go)) <= 1e-9 * scale
+    assert np.max(np.abs(gd - do)) <= 1e-9 * scale
+
+
+def test_adjoint_zero_steps():
+    inst = ti.random_model(2, 2, 62, state="gaussian")
+    L, gg, gd = gpu_grad(inst, 0.3, 0, 1, tcm.TC_GEMM_F64, torch.complex128)
+    assert np.all(gg == 0) and np.all(gd == 0)
+    assert abs(L - oobs.excitation_total(inst.rho0(), inst.n, inst.c)) < 1e-14
+
+
+def test_adjoint_symmetries():
+    """delta = 0, basis-state start: dL/ddelta_i = 0; equal g: equal dL/dg_i."""
+    n, c = 3, 3
+    inst = ti.Instance(n=n, c=c, g=np.full(n, 0.013), omega_a=np.ones(n),
+                       psi0=ti.basis_state(n, c, 0, [1] * n))
+    L, gg, gd = gpu_grad(inst, 0.5, 60, 20, tcm.TC_GEMM_F64, torch.complex128)
+    assert np.max(np.abs(gd)) < 1e-10 * np.max(np.abs(gg))
+    assert np.max(gg) - np.min(gg) < 1e-10 * np.max(np.abs(gg))
+
+
+@pytest.fixture(scope="module")
+def grad8_oracle():
+    w = ti.get("grad8")
+    inst = w.instances[0]
+    T = w.steps * w.dt
+    t0 = time.time()
+    Lo, go, do = ograd.grad_daleckii_krein(inst.n, inst.c, inst.g, inst.omega_a - 1, inst.rho0(), T)
+    fg, fd = ograd.grad_fd(inst.n, inst.c, inst.g, inst.omega_a - 1, inst.rho0(), T, h=1e-6)
+    print(f"oracle gradient (DK + FD) {time.time() - t0:.1f}s", flush=True)
+    return w, inst, Lo, go, do, fg, fd
+
+
+@pytest.mark.parametrize("mode,dtype,tol", [
+    (tcm.TC_GEMM_F32, torch.complex64, 1e-4),
+    (tcm.TC_GEMM_F64, torch.complex128, 1e-9),
+])
+def test_adjoint_grad8_workload(grad8_oracle, mode, dtype, tol):
+    """n=8, c=8 (N=2304), dt=0.05 x 500, checkpoints every 50: complex64 forward and
+    FP32 sweep within 1e-4 of max|grad| (FP64 run within 1e-9) of the oracle's
+    Daleckii-Krein gradient; finite differences agree with both."""
+    w, inst, Lo, go, do, fg, fd = grad8_oracle
+    t0 = time.time()
+    L, gg, gd = gpu_grad(inst, w.dt, w.steps, w.checkpoint_every, mode, dtype)
+    print(f"gpu forward + adjoint mode={mode}: {time.time() - t0:.2f}s", flush=True)
+    scale = max(np.max(np.abs(go)), np.max(np.abs(do)))
+    eg = np.max(np.abs(gg - go)) / scale
+    ed = np.max(np.abs(gd - do)) / scale
+    print(f"grad8 mode={mode}: loss {L:.12f} (oracle {Lo:.12f}), rel err g {eg:.2e}, delta {ed:.2e}",
+          flush=True)
+    assert abs(L - Lo) <= max(tol, 1e-12) * max(1.0, abs(Lo))
+    assert eg <= tol and ed <= tol
+    # the FD reference agrees with the oracle gradient to FD accuracy
+    assert np.max(np.abs(fg - go)) <= 1e-5 * scale and np.max(np.abs(fd - do)) <= 1e-5 * scale
+
+
+def test_autograd_function():
+    inst = ti.random_model(3, 2, 63, delta_sigma=0.01, state="gaussian")
+    g = torch.tensor(inst.g, dtype=torch.float64, requires_grad=True)
+    d = torch.tensor(inst.omega_a - 1, dtype=torch.float64, requires_grad=True)
+    rho0 = torch.from_numpy(inst.rho0()).to("cuda")
+    loss = TCMLoss.apply(g, d, inst.n, inst.c, rho0, 0.4, 30, 10, tcm.TC_GEMM_F64)
+    (2.5 * loss).backward()
+    Lo, go, do = ograd.grad_daleckii_krein(inst.n, inst.c, inst.g, inst.omega_a - 1, inst.rho0(), 12.0)
+    assert abs(float(loss.detach()) - Lo) < 1e-12
+    scale = max(np.max(np.abs(go)), np.max(np.abs(do)))
+    assert np.max(np.abs(g.grad.numpy() - 2.5 * go)) <= 1e-9 * scale
+    assert np.max(np.abs(d.grad.numpy() - 2.5 * do)) <= 1e-9 * scale
