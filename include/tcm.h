@@ -224,6 +224,23 @@ int tc_zgemm(int64_t M, int64_t N, int64_t K, tc_c128 alpha,
  * hi, lo: device uint16 bit patterns.  The rounding used by TC_GEMM_SPLIT_BF16. */
 int tc_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, void* stream);
 
+/* ------------------------------------------------- a8: tile autotuner */
+
+/* tc_evolve with count > 1 and FP64 / FP32 products runs each product phase
+ * of a step as one persistent launch per tile shape over the tiles of every
+ * instance; the shape of each instance comes from a table indexed by its
+ * dimension bucket (N <= 256, <= 1024, <= 4096, larger).  tc_autotune times
+ * both shapes (1: 128 x 128 tiles, 2: 64 x 64 tiles) on an N x N x N complex
+ * product per bucket (N capped at max_N) with hipEvents, stores the faster
+ * one in the process-wide table and, if the environment variable
+ * TC_AUTOTUNE_CACHE names a file, writes the table there; the table is read
+ * from that file on first use.  Synchronises the stream.  ws: device
+ * workspace of tc_autotune_workspace_size bytes (three max_N^2 matrices). */
+int tc_autotune_workspace_size(int32_t gemm_mode, int64_t max_N, size_t* bytes);
+int tc_autotune(int32_t gemm_mode, int64_t max_N, void* ws, size_t ws_bytes, void* stream);
+/* Host-only: the tile shape (1 or 2) the table holds for dimension N. */
+int tc_autotune_query(int32_t gemm_mode, int64_t N, int32_t* variant);
+
 /* ------------------------------------------------------ kernel timing */
 
 /* Kernel classes of tc_profile_read. */

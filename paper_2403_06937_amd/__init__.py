@@ -45,7 +45,8 @@ EXPORTED = [
     "tc_expm_workspace_size", "tc_expm", "tc_evolve_workspace_size", "tc_evolve",
     "tc_observables_workspace_size", "tc_observables", "tc_evolve_backward_workspace_size",
     "tc_evolve_backward", "tc_gemm_workspace_size", "tc_zgemm", "tc_split_bf16",
-    "tc_profile_enable", "tc_profile_read",
+    "tc_profile_enable", "tc_profile_read", "tc_autotune_workspace_size", "tc_autotune",
+    "tc_autotune_query",
 ]
 
 TC_KERNEL_GEMM_F64 = 0
@@ -124,6 +125,9 @@ def lib():
             "tc_split_bf16": [vp, i64, vp, vp, vp],
             "tc_profile_enable": [i32],
             "tc_profile_read": [i32, P(f64), P(i64)],
+            "tc_autotune_workspace_size": [i32, i64, P(sz)],
+            "tc_autotune": [i32, i64, vp, sz, vp],
+            "tc_autotune_query": [i32, i64, P(i32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -326,3 +330,23 @@ def tc_profile_read(kernel: int):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().tc_profile_read(kernel, ctypes.byref(ms), ctypes.byref(n)), "tc_profile_read")
     return ms.value, n.value
+
+
+def tc_autotune_workspace_size(gemm_mode: int, max_N: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().tc_autotune_workspace_size(gemm_mode, max_N, ctypes.byref(b)),
+           "tc_autotune_workspace_size")
+    return b.value
+
+
+def tc_autotune(gemm_mode: int, max_N: int, device="cuda", stream=None):
+    """Times the grouped tile shapes per dimension bucket and fills the table."""
+    ws = _workspace(tc_autotune_workspace_size(gemm_mode, max_N), device)
+    _check(lib().tc_autotune(gemm_mode, max_N, _ptr(ws), ws.numel(), _stream(stream)),
+           "tc_autotune")
+
+
+def tc_autotune_query(gemm_mode: int, N: int) -> int:
+    v = ctypes.c_int32()
+    _check(lib().tc_autotune_query(gemm_mode, N, ctypes.byref(v)), "tc_autotune_query")
+    return v.value

@@ -183,6 +183,38 @@ __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t l
   if (threadIdx.x == 0 && pop) *pop = t;
 }
 
+template <typename E>
+__global__ void grouped_readout_kernel(const ReadoutItem* __restrict__ items,
+                                       const int* __restrict__ counter) {
+  __shared__ double sh[TPB];
+  const ReadoutItem it = items[blockIdx.x];
+  const int r = *counter;
+  const E* __restrict__ rho = static_cast<const E*>(it.rho);
+  const int n = it.n;
+  const int64_t per = int64_t(1) << n;
+  const uint64_t mask = uint64_t(per - 1);
+  double tot = 0.0;
+  for (int mm = 0; mm <= it.c; ++mm) {
+    double part = 0.0, ex = 0.0;
+    for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
+      const double d = double(rho[s * it.ld + s].re);
+      part += d;
+      ex += double(popc64(uint64_t(s) & mask)) * d;
+    }
+    if (it.pdist) {
+      const double pm = block_sum(part, sh);
+      if (threadIdx.x == 0) it.pdist[int64_t(r) * (it.c + 1) + mm] = pm;
+    }
+    tot += ex;
+  }
+  const double t = block_sum(tot, sh);
+  if (threadIdx.x == 0 && it.pop) it.pop[r] = t;
+}
+
+__global__ void advance_counter_kernel(int* counter) {
+  if (threadIdx.x == 0) *counter += 1;
+}
+
 // ---------------------------------------------------- FP64 renormalisation
 template <typename E>
 __global__ void trace_kernel(const E* __restrict__ rho, int64_t ld, int64_t N, double* scratch) {
@@ -628,6 +660,25 @@ int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
   int64_t blocks = (count + TPB - 1) / TPB;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(split_bf16_kernel, dim3(unsigned(blocks)), dim3(TPB), 0, s, x, count, hi, lo);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_grouped_readout(const ReadoutItem* items_dev, int count, bool c128_storage,
+                           const int* counter, hipStream_t s) {
+  if (count == 0) return TC_OK;
+  if (c128_storage)
+    hipLaunchKernelGGL(grouped_readout_kernel<c128>, dim3(unsigned(count)), dim3(TPB), 0, s,
+                       items_dev, counter);
+  else
+    hipLaunchKernelGGL(grouped_readout_kernel<c64>, dim3(unsigned(count)), dim3(TPB), 0, s,
+                       items_dev, counter);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_advance_counter(int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(advance_counter_kernel, dim3(1), dim3(64), 0, s, counter);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }

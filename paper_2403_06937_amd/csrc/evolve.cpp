@@ -10,6 +10,7 @@
 #include "gemm_mfma.h"
 #include "gemm_bf16.h"
 #include "kernels.h"
+#include "profile.h"
 
 namespace tcm {
 namespace {
@@ -237,6 +238,157 @@ int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipS
   return finish(p, in, o, s);
 }
 
+// ------------------------------------------------------------------ batching
+// count > 1 instances with FP64 / FP32 products: each product phase of a step
+// is one persistent grouped launch per tile shape over every instance's
+// tiles, the readout is one launch for all instances (record index kept in a
+// device counter), and with use_graph the launches of a chunk of steps are
+// captured once in a hipGraph and replayed.
+struct BatchBufs {
+  char* items = nullptr;          // 4 groups of count GroupItem descriptors
+  ReadoutItem* ritems = nullptr;  // count readout descriptors
+  int* counter = nullptr;         // record index
+};
+
+bool use_batched(int count, const tc_evolve_opts& o) {
+  return count > 1 && o.gemm_mode != TC_GEMM_SPLIT_BF16;
+}
+
+void plan_batch(Arena& ar, int count, BatchBufs* b) {
+  b->items = static_cast<char*>(ar.take(4 * grouped_bytes(count)));
+  b->ritems = static_cast<ReadoutItem*>(ar.take(size_t(count) * sizeof(ReadoutItem)));
+  b->counter = static_cast<int*>(ar.take(sizeof(int)));
+}
+
+void step_descs(const InstPlan& p, const tc_evolve_opts& o, GemmDesc& g1, GemmDesc& g2) {
+  const bool rot = o.frame == TC_FRAME_ROTATING;
+  g1 = GemmDesc();
+  g1.M = g1.N = g1.K = p.N;
+  g1.A = p.op; g1.lda = p.ldop; g1.a_kmaj = false;
+  g1.B = p.rho; g1.ldb = p.ldr; g1.b_kmaj = true;
+  g1.C = p.X; g1.ldc = p.ldx;
+  if (rot) { g1.Cin = p.rho; g1.ldcin = p.ldr; g1.beta_re = 1.0; }
+  g2 = GemmDesc();
+  g2.M = g2.N = g2.K = p.N;
+  g2.A = p.X; g2.lda = p.ldx; g2.a_kmaj = false;
+  g2.B = p.op; g2.ldb = p.ldop; g2.b_kmaj = true; g2.conj_b = true;
+  g2.C = p.rho; g2.ldc = p.ldr;
+  if (rot) { g2.Cin = p.X; g2.ldcin = p.ldx; g2.beta_re = 1.0; }
+}
+
+int64_t gcd64(int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; }
+
+int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int count,
+                   const tc_evolve_opts& o, const BatchBufs& bb, hipStream_t s) {
+  const bool f64 = o.gemm_mode == TC_GEMM_F64;
+  for (int b = 0; b < count; ++b) TC_RETURN_IF(prepare(plans[b], inst[b], o, s));
+  // group the products by tile shape (autotuner table per dimension bucket)
+  std::vector<GemmDesc> d1[3], d2[3];
+  for (int b = 0; b < count; ++b) {
+    GemmDesc g1, g2;
+    step_descs(plans[b], o, g1, g2);
+    const int v = tile_variant_for(plans[b].N, f64);
+    d1[v].push_back(g1);
+    d2[v].push_back(g2);
+  }
+  GroupedProducts G1[3], G2[3];
+  char* it = bb.items;
+  for (int v = 1; v <= 2; ++v) {
+    if (d1[v].empty()) continue;
+    TC_RETURN_IF(grouped_build(d1[v], f64, v, it, &G1[v], s));
+    it += grouped_bytes(count);
+    TC_RETURN_IF(grouped_build(d2[v], f64, v, it, &G2[v], s));
+    it += grouped_bytes(count);
+  }
+  bool rec = false, ckpt = false;
+  std::vector<ReadoutItem> ri(count);
+  for (int b = 0; b < count; ++b) {
+    ri[b].rho = plans[b].rho;
+    ri[b].ld = plans[b].ldr;
+    ri[b].n = plans[b].m.n;
+    ri[b].c = plans[b].m.c;
+    ri[b].pop = inst[b].pop_out;
+    ri[b].pdist = inst[b].photon_dist_out;
+    rec = rec || inst[b].pop_out || inst[b].photon_dist_out;
+    ckpt = ckpt || inst[b].checkpoints;
+  }
+  TC_TRY_HIP(hipMemcpyAsync(bb.ritems, ri.data(), ri.size() * sizeof(ReadoutItem),
+                            hipMemcpyHostToDevice, s));
+  TC_TRY_HIP(hipMemsetAsync(bb.counter, 0, sizeof(int), s));
+  TC_TRY_HIP(hipStreamSynchronize(s));   // ri is host memory of this call
+  const bool c128s = f64;
+  if (rec) {
+    TC_RETURN_IF(launch_grouped_readout(bb.ritems, count, c128s, bb.counter, s));
+    TC_RETURN_IF(launch_advance_counter(bb.counter, s));
+  }
+  for (int b = 0; b < count; ++b)
+    if (inst[b].checkpoints) TC_RETURN_IF(copy_checkpoint(plans[b], inst[b], o, 0, 0.0, s));
+
+  auto one_step = [&](int64_t st, hipStream_t q) -> int {
+    for (int v = 1; v <= 2; ++v) TC_RETURN_IF(grouped_run(G1[v], q));
+    for (int v = 1; v <= 2; ++v) TC_RETURN_IF(grouped_run(G2[v], q));
+    if (o.renorm_every > 0 && st % o.renorm_every == 0)
+      for (int b = 0; b < count; ++b) TC_RETURN_IF(renorm(plans[b], o, q));
+    if (rec && st % o.record_every == 0) {
+      TC_RETURN_IF(launch_grouped_readout(bb.ritems, count, c128s, bb.counter, q));
+      TC_RETURN_IF(launch_advance_counter(bb.counter, q));
+    }
+    if (ckpt && o.checkpoint_every > 0 && st % o.checkpoint_every == 0)
+      for (int b = 0; b < count; ++b)
+        if (inst[b].checkpoints)
+          TC_RETURN_IF(copy_checkpoint(plans[b], inst[b], o, st / o.checkpoint_every,
+                                       double(st) * o.dt, q));
+    return TC_OK;
+  };
+
+  // the step pattern repeats with period L = lcm(record_every, renorm_every)
+  int64_t L = 1;
+  if (rec && o.record_every > 0) L = o.record_every;
+  if (o.renorm_every > 0) L = L / gcd64(L, o.renorm_every) * o.renorm_every;
+  const int64_t chunk = L * std::max<int64_t>(1, 16 / L);
+  const bool graph = o.use_graph && !ckpt && chunk <= 256 && o.steps >= chunk;
+  if (!graph) {
+    for (int64_t st = 1; st <= o.steps; ++st) TC_RETURN_IF(one_step(st, s));
+  } else {
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    TC_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    int rc = TC_OK;
+    auto hip_ok = [&](hipError_t e, const char* what) {
+      if (e != hipSuccess && rc == TC_OK) {
+        set_error(std::string("hipGraph step chunk: ") + what + ": " + hipGetErrorString(e));
+        rc = TC_ERR_HIP;
+      }
+      return e == hipSuccess;
+    };
+    if (hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
+        hip_ok(hipEventRecord(ev, s), "record") && hip_ok(hipStreamWaitEvent(cs, ev, 0), "wait") &&
+        hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) {
+      profile_suspend(true);
+      for (int64_t st = 1; st <= chunk && rc == TC_OK; ++st) rc = one_step(st, cs);
+      profile_suspend(false);
+      const bool ended = hip_ok(hipStreamEndCapture(cs, &gr), "end capture");
+      if (rc == TC_OK && ended && hip_ok(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0), "instantiate")) {
+        const int64_t reps = o.steps / chunk;
+        for (int64_t r = 0; r < reps && rc == TC_OK; ++r) hip_ok(hipGraphLaunch(ex, cs), "launch");
+        for (int64_t st = reps * chunk + 1; st <= o.steps && rc == TC_OK; ++st) rc = one_step(st, cs);
+      }
+      hip_ok(hipEventRecord(ev, cs), "record");
+      hip_ok(hipStreamWaitEvent(s, ev, 0), "wait");
+      hip_ok(hipStreamSynchronize(cs), "sync");
+    }
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (gr) (void)hipGraphDestroy(gr);
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(cs);
+    TC_RETURN_IF(rc);
+  }
+  for (int b = 0; b < count; ++b) TC_RETURN_IF(finish(plans[b], inst[b], o, s));
+  return TC_OK;
+}
+
 }  // namespace
 }  // namespace tcm
 
@@ -257,6 +409,10 @@ int tc_evolve_workspace_size(const tc_instance* inst, int32_t count, const tc_ev
     TC_RETURN_IF(validate_instance(&inst[b], o, &m));
     InstPlan p;
     plan_instance(inst[b], *o, m, ar, &p);
+  }
+  if (use_batched(count, *o)) {
+    BatchBufs bb;
+    plan_batch(ar, count, &bb);
   }
   *bytes = ar.used;
   return TC_OK;
@@ -280,7 +436,13 @@ int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o, v
     TC_RETURN_IF(validate_instance(&inst[b], o, &m));
     plan_instance(inst[b], *o, m, ar, &plans[b]);
   }
-  for (int b = 0; b < count; ++b) TC_RETURN_IF(evolve_one(plans[b], inst[b], *o, s));
+  if (use_batched(count, *o)) {
+    BatchBufs bb;
+    plan_batch(ar, count, &bb);
+    TC_RETURN_IF(evolve_batched(plans, inst, count, *o, bb, s));
+  } else {
+    for (int b = 0; b < count; ++b) TC_RETURN_IF(evolve_one(plans[b], inst[b], *o, s));
+  }
   if (o->renorm_every > 0 && o->steps >= o->renorm_every) {
     // one flag read per call: a renormalisation met a non-finite or non-positive trace
     for (int b = 0; b < count; ++b) {

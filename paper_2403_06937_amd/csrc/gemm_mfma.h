@@ -1,5 +1,7 @@
 // Dense MFMA matrix products for FP64 and FP32 (complex and real).
 #pragma once
+#include <vector>
+
 #include "common.h"
 
 namespace tcm {
@@ -30,5 +32,25 @@ struct GemmDesc {
 
 int gemm_f64(const GemmDesc& d, hipStream_t s);   // elements double / cplx<double>
 int gemm_f32(const GemmDesc& d, hipStream_t s);   // elements float / cplx<float>
+
+// Grouped complex products (A and B row-major, the layout of the time step):
+// every product of the group shares one tile shape and one persistent launch.
+//   variant 1: 128 x 128 tiles, 8 waves;  variant 2: 64 x 64 tiles, 4 waves.
+struct GroupedProducts {
+  int variant = 1;
+  bool f64 = false;
+  int count = 0;
+  int total_tiles = 0;
+  void* items_dev = nullptr;   // device copy of the descriptors (grouped_bytes(count))
+};
+size_t grouped_bytes(int count);
+// Builds the descriptors of ds and uploads them to items_dev (synchronises s).
+int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* items_dev,
+                  GroupedProducts* g, hipStream_t s);
+int grouped_run(const GroupedProducts& g, hipStream_t s);
+
+// Tile variant for an N x N x N complex product, from the autotuner's table
+// (or its defaults when no tuning ran and no cache file is set).
+int tile_variant_for(int64_t N, bool f64);
 
 }  // namespace tcm

@@ -23,6 +23,7 @@
 #include "gemm_mfma.h"
 #include "profile.h"
 
+#include <algorithm>
 #include <cstdlib>
 
 namespace tcm {
@@ -97,10 +98,12 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
   tn = in_group / gsize;
 }
 
+// One BM x BN output tile (tm, tn) of the product described by p.  Shared by
+// the one-product kernel and the persistent grouped kernel; the caller must
+// separate two calls in one workgroup by a barrier (the LDS is reused).
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
           int BM, int BN, int BKT, int WM, int WN>
-__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
-gemm_kernel(const Params p) {
+__device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn) {
   typedef typename elem<T, CPLX>::type E;
   typedef typename acc_t<T>::type A4;
   constexpr int WGN = BN / (16 * WN);
@@ -129,8 +132,6 @@ gemm_kernel(const Params p) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  int tm, tn;
-  tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
 
   // Staging pattern: element j of this thread sits at (ka + j*dka, ma + j*dma)
@@ -267,6 +268,46 @@ gemm_kernel(const Params p) {
       }
 }
 
+template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
+          int BM, int BN, int BKT, int WM, int WN>
+__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
+gemm_kernel(const Params p) {
+  int tm, tn;
+  tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN>(p, tm, tn);
+}
+
+// Persistent grouped products: items[0 .. count) each describe one product
+// and the first index of its tiles in the concatenated tile list
+// (tile_begin ascending).  The grid is sized to the workgroups the device
+// keeps resident; workgroup w takes tiles w, w + gridDim.x, ... until the
+// list ends, so every workgroup exits after a bounded number of tiles.
+struct GroupItem {
+  Params p;
+  int tile_begin;
+  int exact;        // M, N multiples of the tile and K of the K tile
+};
+
+template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN>
+__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
+grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = count - 1;          // last item with tile_begin <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const Params p = items[lo].p;
+    const int local = t - items[lo].tile_begin;
+    const int tm = local / p.tiles_n, tn = local % p.tiles_n;
+    if (items[lo].exact)
+      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN>(p, tm, tn);
+    else
+      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN>(p, tm, tn);
+    __syncthreads();
+  }
+}
+
 // Tile shapes (BM, BN, BKT, WM, WN); the wave count is (BM/16WM)(BN/16WN).
 struct ShapeDesc { int BM, BN, BKT, WM, WN; };
 
@@ -354,7 +395,109 @@ int launch2(const GemmDesc& d, hipStream_t s) {
   return launch_shape<T, CPLX, false, false, typename V::V0>(d, s);
 }
 
+template <typename S>
+Params make_params(const GemmDesc& d) {
+  Params p;
+  p.M = d.M; p.N = d.N; p.K = d.K;
+  p.A = d.A; p.lda = d.lda; p.B = d.B; p.ldb = d.ldb;
+  p.C = d.C; p.ldc = d.ldc; p.Cin = d.Cin; p.ldcin = d.ldcin;
+  p.alpha_re = d.alpha_re; p.alpha_im = d.alpha_im;
+  p.beta_re = d.beta_re; p.beta_im = d.beta_im; p.gamma = d.gamma;
+  p.conj_a = d.conj_a; p.conj_b = d.conj_b; p.c_trans = d.c_trans; p.cin_trans = d.cin_trans;
+  p.tiles_m = int((d.M + S::BM - 1) / S::BM);
+  p.tiles_n = int((d.N + S::BN - 1) / S::BN);
+  return p;
+}
+
+template <typename S>
+int build_items(const std::vector<GemmDesc>& ds, std::vector<GroupItem>& items, int* total) {
+  int64_t t = 0;
+  items.clear();
+  for (const GemmDesc& d : ds) {
+    if (d.a_kmaj || !d.b_kmaj || !d.complex) {
+      set_error("grouped products take A and B row-major, complex");
+      return TC_ERR_UNSUPPORTED;
+    }
+    GroupItem it;
+    it.p = make_params<S>(d);
+    it.tile_begin = int(t);
+    it.exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
+    t += int64_t(it.p.tiles_m) * it.p.tiles_n;
+    items.push_back(it);
+  }
+  if (t > (int64_t(1) << 30)) { set_error("too many tiles in one group"); return TC_ERR_UNSUPPORTED; }
+  *total = int(t);
+  return TC_OK;
+}
+
+int device_cus() {
+  static int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return n > 0 ? n : 256;
+  }();
+  return cus;
+}
+
+template <typename T, typename S>
+int grouped_launch_t(const GroupedProducts& g, hipStream_t s) {
+  auto kern = grouped_gemm_kernel<T, true, false, true, S::BM, S::BN, S::BKT, S::WM, S::WN>;
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    int nb = 0;
+    TC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, S::NT, 0));
+    per_cu = nb > 0 ? nb : 1;
+  }
+  const int64_t resident = int64_t(device_cus()) * per_cu;
+  const int grid = int(std::min<int64_t>(g.total_tiles, resident));
+  if (grid <= 0) return TC_OK;
+  ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(unsigned(S::NT)), 0, s,
+                     static_cast<const GroupItem*>(g.items_dev), g.count, g.total_tiles);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
 }  // namespace
+
+size_t grouped_bytes(int count) { return size_t(count) * sizeof(GroupItem); }
+
+int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* items_dev,
+                  GroupedProducts* g, hipStream_t s) {
+  std::vector<GroupItem> items;
+  int total = 0;
+  if (variant != 1 && variant != 2) { set_error("grouped tile variant must be 1 or 2"); return TC_ERR_INVALID_ARGUMENT; }
+  typedef Variants<double, true> VD;
+  typedef Variants<float, true> VF;
+  int rc;
+  if (f64)
+    rc = variant == 1 ? build_items<VD::V1>(ds, items, &total) : build_items<VD::V2>(ds, items, &total);
+  else
+    rc = variant == 1 ? build_items<VF::V1>(ds, items, &total) : build_items<VF::V2>(ds, items, &total);
+  TC_RETURN_IF(rc);
+  g->variant = variant;
+  g->f64 = f64;
+  g->count = int(items.size());
+  g->total_tiles = total;
+  g->items_dev = items_dev;
+  if (!items.empty()) {
+    // one synchronous upload per call; the descriptors are reused by every step
+    TC_TRY_HIP(hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(GroupItem),
+                              hipMemcpyHostToDevice, s));
+    TC_TRY_HIP(hipStreamSynchronize(s));
+  }
+  return TC_OK;
+}
+
+int grouped_run(const GroupedProducts& g, hipStream_t s) {
+  if (g.count == 0 || g.total_tiles == 0) return TC_OK;
+  if (g.f64)
+    return g.variant == 1 ? grouped_launch_t<double, Variants<double, true>::V1>(g, s)
+                          : grouped_launch_t<double, Variants<double, true>::V2>(g, s);
+  return g.variant == 1 ? grouped_launch_t<float, Variants<float, true>::V1>(g, s)
+                        : grouped_launch_t<float, Variants<float, true>::V2>(g, s);
+}
 
 int gemm_f64(const GemmDesc& d, hipStream_t s) {
   if (d.M == 0 || d.N == 0) return TC_OK;

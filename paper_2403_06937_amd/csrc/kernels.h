@@ -43,6 +43,19 @@ int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double*
 int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
                        double* pdist, hipStream_t s);
 
+// Readout of many instances in one launch (one workgroup each): record index
+// r = *counter; pop[r] and pdist[r*(c+1) + m] as above.  advance_counter adds 1.
+struct ReadoutItem {
+  const void* rho;
+  int64_t ld;
+  int n, c;
+  double* pop;      // may be NULL
+  double* pdist;    // may be NULL
+};
+int launch_grouped_readout(const ReadoutItem* items_dev, int count, bool c128_storage,
+                           const int* counter, hipStream_t s);
+int launch_advance_counter(int* counter, hipStream_t s);
+
 // Hermitise and divide by Re Tr rho, in FP64.  scratch: device double[2]
 // (trace, non-finite flag).  For c64 storage the arithmetic is FP64 too.
 int launch_renorm_c128(c128* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s);

@@ -40,7 +40,11 @@ void release_all() {
 
 }  // namespace
 
-bool profile_enabled() { return g_on.load(std::memory_order_relaxed); }
+thread_local bool t_suspended = false;
+
+bool profile_enabled() { return g_on.load(std::memory_order_relaxed) && !t_suspended; }
+
+void profile_suspend(bool on) { t_suspended = on; }
 
 void profile_begin(int kind, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);

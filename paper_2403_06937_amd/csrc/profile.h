@@ -5,6 +5,8 @@
 namespace tcm {
 
 bool profile_enabled();
+// While suspended (e.g. during hipGraph capture) no events are recorded.
+void profile_suspend(bool on);
 // Records an event on s before the launch (begin) and after it (end).
 void profile_begin(int kind, hipStream_t s);
 void profile_end(int kind, hipStream_t s);
