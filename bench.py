@@ -92,6 +92,99 @@ def run_mode(tcm, pipeline, model, U, rho0_np, mode, frame, dtype, steps, warmup
             "rho": rho, "pop": pop}
 
 
+def bench_n9(tcm, pipeline, ti, steps=100):
+    """n=9, c=9 (N=5120) FP64 workload: steps/s and TFLOP/s of its full 100-step run."""
+    import torch
+    w = ti.get("n9")
+    inst = w.instances[0]
+    m = pipeline.model_of(inst)
+    _, U = pipeline.propagator(m, w.dt)
+    rho = torch.from_numpy(inst.rho0()).to("cuda")
+    pipeline.evolve(m, U, rho.clone(), 2, w.dt)                   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    pipeline.evolve(m, U, rho, steps, w.dt)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": w.name, "N": inst.N, "dtype": "f64", "steps": steps,
+            "steps_per_s": 1000.0 / ms, "ms_per_step": ms,
+            "tflops": 16.0 * inst.N ** 3 / (ms * 1e-3) / 1e12}
+
+
+def bench_batch64(tcm, pipeline, ti, steps=50):
+    """64 uneven instances (N = 32..7168, complex64) stepped together: grouped
+    persistent launches with autotuned tile shapes, hipGraph-captured chunks."""
+    import torch
+    w = ti.get("batch64")
+    models = [pipeline.model_of(i) for i in w.instances]
+    Us = [pipeline.propagator(m, w.dt)[1] for m in models]
+    maxN = max(m.N for m in models)
+    t0 = time.perf_counter()
+    tcm.tc_autotune(tcm.TC_GEMM_F32, maxN)
+    tune_s = time.perf_counter() - t0
+    rho0 = [torch.from_numpy(i.rho0()).to("cuda").to(torch.complex64) for i in w.instances]
+
+    def run(k):
+        rhos = [r.clone() for r in rho0]
+        pops = [torch.zeros(k + 1, dtype=torch.float64, device="cuda") for _ in models]
+        opts = tcm.make_opts(k, w.dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_ROTATING, 0, 1, 0, 1)
+        insts = [tcm.make_instance(m, U, r, p) for m, U, r, p in zip(models, Us, rhos, pops)]
+        ws = torch.empty(tcm.tc_evolve_workspace_size(insts, opts), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tcm.tc_evolve(insts, opts, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    run(16)                                                      # warm-up
+    ms = run(steps)
+    flop = 16.0 * sum(float(m.N) ** 3 for m in models) * steps
+    return {"workload": w.name, "instances": len(models), "N_min": min(m.N for m in models),
+            "N_max": maxN, "dtype": "f32", "steps": steps, "steps_per_s": steps / (ms * 1e-3),
+            "ms_per_step": ms / steps, "tflops": flop / (ms * 1e-3) / 1e12,
+            "autotune_s": tune_s,
+            "tile_variants": {str(b): tcm.tc_autotune_query(tcm.TC_GEMM_F32, b)
+                              for b in (256, 1024, 4096, 7168)}}
+
+
+def bench_grad8(tcm, pipeline, ti):
+    """n=8, c=8 (N=2304): complex64 forward with checkpoints every 50 (500 steps,
+    rotating frame) and the adjoint sweep (FP32 products, FP64 Frechet)."""
+    import torch
+    w = ti.get("grad8")
+    inst = w.instances[0]
+    m = pipeline.model_of(inst)
+    H, U = pipeline.propagator(m, w.dt)
+    rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    pipeline.evolve(m, U, rho.clone(), 4, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING)  # warm-up
+    torch.cuda.synchronize()
+    ev[0].record()
+    _, _, ck = pipeline.evolve(m, U, rho, w.steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING,
+                               0, w.steps, w.checkpoint_every)
+    ev[1].record()
+    opts = tcm.make_opts(w.steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_LAB, 0, 1,
+                         w.checkpoint_every)
+    gg = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    gd = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(tcm.tc_evolve_backward_workspace_size(m, opts), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    ev[2].record()
+    tcm.tc_evolve_backward(m, H, U, opts, ck, loss, gg, gd, ws=ws)
+    ev[3].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1])
+    bwd = ev[2].elapsed_time(ev[3])
+    return {"workload": w.name, "N": inst.N, "steps": w.steps, "dtype": "f32",
+            "forward_s": fwd / 1000.0, "backward_s": bwd / 1000.0,
+            "backward_over_forward": bwd / fwd, "loss": float(loss.item())}
+
+
 def cpu_baseline(U_np, rho_np, target_s=12.0):
     """The oracle's dense step (U rho U^dag with numpy products) on a row slab of
     the same N = 12288 matrices, timed on the host cores; scaled to steps/s."""
@@ -127,6 +220,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="split,fp64,fp32")
+    ap.add_argument("--extras", default="n9,batch64,grad8",
+                    help="other workloads measured after the headline one ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -232,6 +327,16 @@ def main():
         U_np = U.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(U_np, rho0)
         del U_np
+    del U
+    torch.cuda.empty_cache()
+    extras = [e for e in args.extras.split(",") if e]
+    if extras:
+        out["other_workloads"] = {}
+    for e in extras:
+        fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8}[e]
+        out["other_workloads"][e] = fn(tcm, pipeline, ti)
+        log(f"{e}: {out['other_workloads'][e]}")
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
