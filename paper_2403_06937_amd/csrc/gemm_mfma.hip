@@ -77,11 +77,13 @@ constexpr int GROUP_M = 8;
 
 // Default tile variant per element type for the step / exponential layout,
 // chosen by timing every variant at N = 12288 on gfx950:
-//   complex FP64: 64x64 tiles, 4 waves (285 ms per product; 128x64: 438 ms)
+//   complex FP64: 128x128 tiles, 8 waves, K tile 16 (240 ms per product;
+//                 64x64: 285 ms; 128x128 with K tile 8: 294 ms; 128x64: 438 ms;
+//                 LDS row padding of 0, 16 or 32 bytes: no difference)
 //   real FP64:    128x128 tiles, 8 waves (U formation 1.07 s; 128x64: 1.42 s)
 //   complex FP32: 128x128 tiles, 8 waves (112 ms; 128x64: 118 ms)
 template <typename T, bool CPLX> struct DefaultVariant { static constexpr int value = 1; };
-template <> struct DefaultVariant<double, true> { static constexpr int value = 2; };
+template <> struct DefaultVariant<double, true> { static constexpr int value = 6; };
 
 // Tile coordinates of this workgroup (XCD-contiguous, grouped ordering).
 __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
@@ -102,7 +104,7 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
 // the one-product kernel and the persistent grouped kernel; the caller must
 // separate two calls in one workgroup by a barrier (the LDS is reused).
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
-          int BM, int BN, int BKT, int WM, int WN>
+          int BM, int BN, int BKT, int WM, int WN, int PADB>
 __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn) {
   typedef typename elem<T, CPLX>::type E;
   typedef typename acc_t<T>::type A4;
@@ -110,7 +112,7 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn) {
   constexpr int WGM = BM / (16 * WM);
   constexpr int NT = 64 * WGM * WGN;          // threads per workgroup
   static_assert(BKT % 4 == 0, "K tile is a multiple of the MFMA depth");
-  constexpr int PADE = 16 / sizeof(E) > 0 ? 16 / sizeof(E) : 1;  // 16 bytes of padding
+  constexpr int PADE = PADB / int(sizeof(E));   // LDS row padding in elements
   constexpr int LDA_S = BM + PADE;
   constexpr int LDB_S = BN + PADE;
   constexpr int A_PT = BKT * BM / NT;          // staged elements per thread
@@ -269,12 +271,12 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn) {
 }
 
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
-          int BM, int BN, int BKT, int WM, int WN>
+          int BM, int BN, int BKT, int WM, int WN, int PADB>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
 gemm_kernel(const Params p) {
   int tm, tn;
   tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
-  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN>(p, tm, tn);
+  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN, PADB>(p, tm, tn);
 }
 
 // Persistent grouped products: items[0 .. count) each describe one product
@@ -288,7 +290,8 @@ struct GroupItem {
   int exact;        // M, N multiples of the tile and K of the K tile
 };
 
-template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN>
+template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
+          int PADB>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
 grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
@@ -301,9 +304,9 @@ grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
     const int local = t - items[lo].tile_begin;
     const int tm = local / p.tiles_n, tn = local % p.tiles_n;
     if (items[lo].exact)
-      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN>(p, tm, tn);
+      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn);
     else
-      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN>(p, tm, tn);
+      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN, PADB>(p, tm, tn);
     __syncthreads();
   }
 }
@@ -311,8 +314,8 @@ grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
 // Tile shapes (BM, BN, BKT, WM, WN); the wave count is (BM/16WM)(BN/16WN).
 struct ShapeDesc { int BM, BN, BKT, WM, WN; };
 
-template <int BM_, int BN_, int BKT_, int WM_, int WN_> struct Shp {
-  static constexpr int BM = BM_, BN = BN_, BKT = BKT_, WM = WM_, WN = WN_;
+template <int BM_, int BN_, int BKT_, int WM_, int WN_, int PADB_ = 16> struct Shp {
+  static constexpr int BM = BM_, BN = BN_, BKT = BKT_, WM = WM_, WN = WN_, PADB = PADB_;
   static constexpr int NT = 64 * (BM / (16 * WM)) * (BN / (16 * WN));
 };
 
@@ -324,24 +327,36 @@ template <> struct Variants<double, true> {
   typedef Shp<128, 128, 8, 4, 2> V1;
   typedef Shp<64, 64, 16, 2, 2> V2;
   typedef Shp<128, 128, 8, 2, 4> V3;
+  typedef Shp<64, 64, 16, 2, 2, 0> V4;
+  typedef Shp<64, 64, 16, 2, 2, 32> V5;
+  typedef Shp<128, 128, 16, 4, 2> V6;
 };
 template <> struct Variants<double, false> {
   typedef Shp<128, 64, 16, 4, 2> V0;
   typedef Shp<128, 128, 16, 4, 2> V1;
   typedef Shp<64, 64, 16, 2, 2> V2;
   typedef Shp<128, 128, 16, 2, 4> V3;
+  typedef Shp<64, 64, 16, 2, 2, 0> V4;
+  typedef Shp<64, 64, 16, 2, 2, 32> V5;
+  typedef Shp<128, 128, 16, 4, 2, 0> V6;
 };
 template <> struct Variants<float, true> {
   typedef Shp<128, 64, 16, 4, 2> V0;
   typedef Shp<128, 128, 16, 4, 2> V1;
   typedef Shp<64, 64, 16, 2, 2> V2;
   typedef Shp<128, 128, 16, 2, 4> V3;
+  typedef Shp<64, 64, 16, 2, 2, 0> V4;
+  typedef Shp<64, 64, 16, 2, 2, 32> V5;
+  typedef Shp<128, 128, 16, 4, 2, 0> V6;
 };
 template <> struct Variants<float, false> {
   typedef Shp<128, 64, 16, 4, 2> V0;
   typedef Shp<128, 128, 16, 4, 2> V1;
   typedef Shp<64, 64, 16, 2, 2> V2;
   typedef Shp<128, 128, 16, 2, 4> V3;
+  typedef Shp<64, 64, 16, 2, 2, 0> V4;
+  typedef Shp<64, 64, 16, 2, 2, 32> V5;
+  typedef Shp<128, 128, 16, 4, 2, 0> V6;
 };
 
 template <typename T, bool CPLX, bool AK, bool BK, typename S>
@@ -362,10 +377,10 @@ int launch_shape(const GemmDesc& d, hipStream_t s) {
   const dim3 grid{unsigned(tiles), 1u, 1u}, block{unsigned(S::NT), 1u, 1u};
   ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
   if (exact)
-    hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN>),
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN, S::PADB>),
                        grid, block, 0, s, p);
   else
-    hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, true, S::BM, S::BN, S::BKT, S::WM, S::WN>),
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, true, S::BM, S::BN, S::BKT, S::WM, S::WN, S::PADB>),
                        grid, block, 0, s, p);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
@@ -387,6 +402,9 @@ int launch2(const GemmDesc& d, hipStream_t s) {
       case 1: return launch_shape<T, CPLX, false, true, typename V::V1>(d, s);
       case 2: return launch_shape<T, CPLX, false, true, typename V::V2>(d, s);
       case 3: return launch_shape<T, CPLX, false, true, typename V::V3>(d, s);
+      case 4: return launch_shape<T, CPLX, false, true, typename V::V4>(d, s);
+      case 5: return launch_shape<T, CPLX, false, true, typename V::V5>(d, s);
+      case 6: return launch_shape<T, CPLX, false, true, typename V::V6>(d, s);
       default: return launch_shape<T, CPLX, false, true, typename V::V0>(d, s);
     }
   }
@@ -442,7 +460,7 @@ int device_cus() {
 
 template <typename T, typename S>
 int grouped_launch_t(const GroupedProducts& g, hipStream_t s) {
-  auto kern = grouped_gemm_kernel<T, true, false, true, S::BM, S::BN, S::BKT, S::WM, S::WN>;
+  auto kern = grouped_gemm_kernel<T, true, false, true, S::BM, S::BN, S::BKT, S::WM, S::WN, S::PADB>;
   static int per_cu = -1;
   if (per_cu < 0) {
     int nb = 0;
