@@ -154,7 +154,9 @@ typedef struct {
   int32_t record_every;     /* >= 1 when pop_out / photon_dist_out are given        */
   int32_t checkpoint_every; /* 0 = none; else rho after every checkpoint_every-th step */
   int32_t use_graph;        /* capture the per-chunk launches in a hipGraph         */
-  int32_t reserved;
+  int32_t full_product;     /* 0: rho' = X U^dag is Hermitian, so its upper tile
+                               triangle is multiplied and mirrored (rho(0) must be
+                               Hermitian); 1: every tile of both products        */
 } tc_evolve_opts;
 
 int tc_evolve_workspace_size(const tc_instance* inst, int32_t count,

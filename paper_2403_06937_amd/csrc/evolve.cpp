@@ -108,23 +108,16 @@ int renorm(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   return TC_OK;
 }
 
+void step_descs(const InstPlan& p, const tc_evolve_opts& o, GemmDesc& g1, GemmDesc& g2);
+
 // One step of Eq. (6) for FP64 / FP32:
 //   lab:      X = U rho,          rho' = X U^dag = X conj(U)   (U symmetric)
 //   rotating: X = rho + D rho,    rho' = X + X conj(D)         (U~ = I + D symmetric)
+// rho' is Hermitian: unless full_product is set, the second product forms only
+// its upper tile triangle and mirrors it.
 int step_mfma(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
-  const bool rot = o.frame == TC_FRAME_ROTATING;
-  GemmDesc g1;
-  g1.M = g1.N = g1.K = p.N;
-  g1.A = p.op; g1.lda = p.ldop; g1.a_kmaj = false;
-  g1.B = p.rho; g1.ldb = p.ldr; g1.b_kmaj = true;
-  g1.C = p.X; g1.ldc = p.ldx;
-  if (rot) { g1.Cin = p.rho; g1.ldcin = p.ldr; g1.beta_re = 1.0; }
-  GemmDesc g2;
-  g2.M = g2.N = g2.K = p.N;
-  g2.A = p.X; g2.lda = p.ldx; g2.a_kmaj = false;
-  g2.B = p.op; g2.ldb = p.ldop; g2.b_kmaj = true; g2.conj_b = true;
-  g2.C = p.rho; g2.ldc = p.ldr;
-  if (rot) { g2.Cin = p.X; g2.ldcin = p.ldx; g2.beta_re = 1.0; }
+  GemmDesc g1, g2;
+  step_descs(p, o, g1, g2);
   if (o.gemm_mode == TC_GEMM_F64) {
     TC_RETURN_IF(gemm_f64(g1, s));
     TC_RETURN_IF(gemm_f64(g2, s));
@@ -214,7 +207,7 @@ int finish(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStrea
 int step(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
     return step_split(static_cast<c64*>(p.rho), p.ldr, static_cast<c64*>(p.X), p.ldx, p.N,
-                      o.frame == TC_FRAME_ROTATING, p.planes, s);
+                      o.frame == TC_FRAME_ROTATING, o.full_product == 0, p.planes, s);
   return step_mfma(p, o, s);
 }
 
@@ -274,6 +267,7 @@ void step_descs(const InstPlan& p, const tc_evolve_opts& o, GemmDesc& g1, GemmDe
   g2.B = p.op; g2.ldb = p.ldop; g2.b_kmaj = true; g2.conj_b = true;
   g2.C = p.rho; g2.ldc = p.ldr;
   if (rot) { g2.Cin = p.X; g2.ldcin = p.ldx; g2.beta_re = 1.0; }
+  g2.herm = o.full_product == 0;
 }
 
 int64_t gcd64(int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; }

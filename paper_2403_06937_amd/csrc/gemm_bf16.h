@@ -36,7 +36,9 @@ int split_operand(const c64* op, int64_t ld, int64_t N, const SplitPlanes& p, hi
 // Rt from the c64 master state (after preparation and after each renormalisation).
 int split_state(const c64* rho, int64_t ld, int64_t N, const SplitPlanes& p, hipStream_t s);
 // One step rho <- op rho op^dag (lab) or rho <- (I + D) rho (I + D)^dag (rotating).
-int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotating,
+// herm: rho is Hermitian, so the second product forms its upper tile triangle
+// and mirrors it.
+int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotating, bool herm,
                const SplitPlanes& p, hipStream_t s);
 
 // General split product on c64 operands (kernel-level entry point).

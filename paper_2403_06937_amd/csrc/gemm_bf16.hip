@@ -65,16 +65,48 @@ struct SplitParams {
   const c64* Cin; int64_t ldcin; int cin_trans;
   c64* Cf; int64_t ldcf;
   uint16_t* P; int64_t ldp, p_ps; int p_trans;
+  int herm;   // Hermitian result (M == N): upper tile triangle, mirrored stores
   int tiles_m, tiles_n;
 };
 
 constexpr int GROUP_M = 8;
 
-__device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int total = tiles_m * tiles_n;
+// Consecutive workgroup ids go round the 8 XCDs; give each XCD a contiguous
+// run of the tile order so that its tiles share operand rows in its L2.
+__device__ __forceinline__ int xcd_linear(int pid, int total) {
   const int q = total / 8, r = total % 8;
   const int xcd = pid % 8, local = pid / 8;
-  const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+}
+
+// Tile lin of the upper block triangle (tm <= tn) of a T x T tile grid:
+// GROUP_M tile rows at a time, column by column within a group.
+__device__ __forceinline__ void tri_coords(int lin, int T, int& tm, int& tn) {
+  int first = 0;
+  for (;;) {
+    const int gs = min(T - first, GROUP_M);
+    const int tri = gs * (gs - 1) / 2;              // the group's leading triangle
+    const int cnt = gs * (T - first) - tri;
+    if (lin < cnt) {
+      if (lin < tri) {
+        int c = 0;
+        while ((c + 1) * (c + 2) / 2 <= lin) ++c;
+        tn = first + c;
+        tm = first + lin - c * (c + 1) / 2;
+      } else {
+        const int q = lin - tri;
+        tn = first + gs - 1 + q / gs;
+        tm = first + q % gs;
+      }
+      return;
+    }
+    lin -= cnt;
+    first += gs;
+  }
+}
+
+__device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int lin = xcd_linear(pid, tiles_m * tiles_n);
   const int per_group = GROUP_M * tiles_n;
   const int group = lin / per_group;
   const int first_m = group * GROUP_M;
@@ -104,7 +136,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   int tm, tn;
-  tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  if (p.herm)
+    tri_coords(xcd_linear(blockIdx.x, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  else
+    tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = int64_t(tm) * SPLIT_BM, n0 = int64_t(tn) * SPLIT_BN;
 
   // Staging: per plane a 128-row x 32-deep tile is 512 chunks of 16 bytes;
@@ -228,8 +263,9 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
     }
   }
 
-  // epilogue
+  // epilogue; a mirrored tile also stores element (col, row) = conj(row, col)
   const bool use_beta = p.Cin != nullptr && (p.br != 0.f || p.bi != 0.f);
+  const bool mirror = p.herm && tm != tn;
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -252,7 +288,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
         if (!inb) { yr = 0.f; yi = 0.f; }
         vr[r] = yr;
         vi[r] = yi;
-        if (p.Cf && inb) p.Cf[row * p.ldcf + col] = c64{yr, yi};
+        if (p.Cf && inb) {
+          p.Cf[row * p.ldcf + col] = c64{yr, yi};
+          if (mirror) p.Cf[col * p.ldcf + row] = c64{yr, -yi};
+        }
       }
       if (p.P) {
         uint16_t h[4][4];   // [plane][r]
@@ -261,18 +300,26 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
           split2(vr[r], h[PL_RH][r], h[PL_RL][r]);
           split2(vi[r], h[PL_IH][r], h[PL_IL][r]);
         }
-        if (p.p_trans) {
+        // the split of -x is the negated split of x (RNE is symmetric), so the
+        // mirrored element's imaginary planes are the sign-flipped h[PL_I*]
+        const uint16_t neg[4] = {0, 0, 0x8000u, 0x8000u};
+        if (p.p_trans || mirror) {
+          const uint16_t f = p.p_trans ? 0 : 0x8000u;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const u2 v = u2{uint32_t(h[q][0]) | (uint32_t(h[q][1]) << 16),
-                            uint32_t(h[q][2]) | (uint32_t(h[q][3]) << 16)};
+            const uint32_t m = (PL_IH == q || PL_IL == q) ? f : 0;
+            const u2 v = u2{(uint32_t(h[q][0]) | (uint32_t(h[q][1]) << 16)) ^ (m | (m << 16)),
+                            (uint32_t(h[q][2]) | (uint32_t(h[q][3]) << 16)) ^ (m | (m << 16))};
             *reinterpret_cast<u2*>(p.P + q * p.p_ps + col * p.ldp + row0) = v;
           }
-        } else {
+        }
+        if (!p.p_trans || mirror) {
+          const bool flip = p.p_trans;   // here this is the mirrored element
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) p.P[q * p.p_ps + (row0 + r) * p.ldp + col] = h[q][r];
+            for (int r = 0; r < 4; ++r)
+              p.P[q * p.p_ps + (row0 + r) * p.ldp + col] = h[q][r] ^ (flip ? neg[q] : 0);
         }
       }
     }
@@ -346,7 +393,7 @@ int split_variant() {
 
 int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t Kp, float ar,
               float ai, float br, float bi, const c64* Cin, int64_t ldcin, bool cin_trans, c64* Cf,
-              int64_t ldcf, const Planes4* P, bool p_trans, hipStream_t s) {
+              int64_t ldcf, const Planes4* P, bool p_trans, bool herm, hipStream_t s) {
   SplitParams q;
   q.A = A.base; q.lda = A.ld; q.a_ps = A.pstride;
   q.B = B.base; q.ldb = B.ld; q.b_ps = B.pstride;
@@ -356,15 +403,23 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
   q.Cf = Cf; q.ldcf = ldcf;
   q.P = P ? P->base : nullptr; q.ldp = P ? P->ld : 0; q.p_ps = P ? P->pstride : 0;
   q.p_trans = p_trans;
+  q.herm = herm;
   q.tiles_m = int((M + SPLIT_BM - 1) / SPLIT_BM);
   q.tiles_n = int((N + SPLIT_BN - 1) / SPLIT_BN);
-  const int64_t tiles = int64_t(q.tiles_m) * q.tiles_n;
+  if (herm && M != N) {
+    set_error("split product: a Hermitian result must be square");
+    return TC_ERR_INVALID_ARGUMENT;
+  }
+  const int64_t tiles = herm ? int64_t(q.tiles_m) * (q.tiles_m + 1) / 2
+                             : int64_t(q.tiles_m) * q.tiles_n;
   if (tiles == 0) return TC_OK;
   // the padded planes must cover every tile row / column and the K extent
   if (A.rows < int64_t(q.tiles_m) * SPLIT_BM || B.rows < int64_t(q.tiles_n) * SPLIT_BN ||
       A.ld < Kp || B.ld < Kp || Kp % SPLIT_BK != 0 ||
       (P && (P->rows < (p_trans ? int64_t(q.tiles_n) * SPLIT_BN : int64_t(q.tiles_m) * SPLIT_BM) ||
-             P->ld < (p_trans ? int64_t(q.tiles_m) * SPLIT_BM : int64_t(q.tiles_n) * SPLIT_BN)))) {
+             P->ld < (p_trans ? int64_t(q.tiles_m) * SPLIT_BM : int64_t(q.tiles_n) * SPLIT_BN) ||
+             (herm && (P->rows < int64_t(q.tiles_m) * SPLIT_BM ||
+                       P->ld < int64_t(q.tiles_m) * SPLIT_BM))))) {
     set_error("split product: plane buffers do not cover the padded tiles");
     return TC_ERR_INVALID_ARGUMENT;
   }
@@ -404,16 +459,17 @@ int split_state(const c64* rho, int64_t ld, int64_t N, const SplitPlanes& p, hip
   return split_into(rho, ld, N, N, true, false, p.Rt, s);
 }
 
-int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotating,
+int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotating, bool herm,
                const SplitPlanes& p, hipStream_t s) {
   // X = op rho (+ rho): A = split(op), B = split(rho^T); planes of X row-major
   TC_RETURN_IF(run_split(p.opA, p.Rt, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
                          rotating ? rho : nullptr, ldr, false, rotating ? X : nullptr, ldx,
-                         &p.X, false, s));
+                         &p.X, false, false, s));
   // rho' = X conj(op) (+ X): A = split(X), B = split(conj(op)^T); FP32 rho and
-  // transposed planes of rho for the next step
+  // transposed planes of rho for the next step.  rho' is Hermitian, so with
+  // herm only its upper tile triangle is multiplied.
   TC_RETURN_IF(run_split(p.X, p.opB, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
-                         rotating ? X : nullptr, ldx, false, rho, ldr, &p.Rt, true, s));
+                         rotating ? X : nullptr, ldx, false, rho, ldr, &p.Rt, true, herm, s));
   return TC_OK;
 }
 
@@ -441,7 +497,7 @@ int split_gemm(const GemmDesc& d, const SplitGemmPlan& p, hipStream_t s) {
   }
   return run_split(p.A, p.B, d.M, d.N, p.A.ld, float(d.alpha_re), float(d.alpha_im),
                    float(d.beta_re), float(d.beta_im), static_cast<const c64*>(d.Cin), d.ldcin,
-                   d.cin_trans, static_cast<c64*>(d.C), d.ldc, nullptr, false, s);
+                   d.cin_trans, static_cast<c64*>(d.C), d.ldc, nullptr, false, d.herm, s);
 }
 
 }  // namespace tcm

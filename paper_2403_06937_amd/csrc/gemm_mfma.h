@@ -28,6 +28,10 @@ struct GemmDesc {
   double beta_re = 0.0, beta_im = 0.0;
   double gamma = 0.0;       // added to the real part of the diagonal (m == n)
   bool complex = true;
+  // The caller guarantees that C is Hermitian (symmetric when real), M == N:
+  // only the tiles on and above the tile diagonal are computed, and each
+  // off-diagonal tile also stores its conjugate transpose.
+  bool herm = false;
 };
 
 int gemm_f64(const GemmDesc& d, hipStream_t s);   // elements double / cplx<double>

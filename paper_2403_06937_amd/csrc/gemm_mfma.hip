@@ -70,6 +70,7 @@ struct Params {
   const void* Cin; int64_t ldcin;
   double alpha_re, alpha_im, beta_re, beta_im, gamma;
   int conj_a, conj_b, c_trans, cin_trans;
+  int herm;
   int tiles_m, tiles_n;
 };
 
@@ -85,12 +86,43 @@ constexpr int GROUP_M = 8;
 template <typename T, bool CPLX> struct DefaultVariant { static constexpr int value = 1; };
 template <> struct DefaultVariant<double, true> { static constexpr int value = 6; };
 
-// Tile coordinates of this workgroup (XCD-contiguous, grouped ordering).
-__device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int total = tiles_m * tiles_n;
+// Consecutive workgroup ids go round the 8 XCDs; give each XCD a contiguous
+// run of the tile order so that its tiles share operand rows in its L2.
+__device__ __forceinline__ int xcd_linear(int pid, int total) {
   const int q = total / 8, r = total % 8;
   const int xcd = pid % 8, local = pid / 8;
-  const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+}
+
+// Tile lin of the upper block triangle (tm <= tn) of a T x T tile grid:
+// GROUP_M tile rows at a time, column by column within a group.
+__device__ __forceinline__ void tri_coords(int lin, int T, int& tm, int& tn) {
+  int first = 0;
+  for (;;) {
+    const int gs = min(T - first, GROUP_M);
+    const int tri = gs * (gs - 1) / 2;              // the group's leading triangle
+    const int cnt = gs * (T - first) - tri;
+    if (lin < cnt) {
+      if (lin < tri) {
+        int c = 0;
+        while ((c + 1) * (c + 2) / 2 <= lin) ++c;
+        tn = first + c;
+        tm = first + lin - c * (c + 1) / 2;
+      } else {
+        const int q = lin - tri;
+        tn = first + gs - 1 + q / gs;
+        tm = first + q % gs;
+      }
+      return;
+    }
+    lin -= cnt;
+    first += gs;
+  }
+}
+
+// Tile coordinates of this workgroup (XCD-contiguous, grouped ordering).
+__device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int lin = xcd_linear(pid, tiles_m * tiles_n);
   const int per_group = GROUP_M * tiles_n;
   const int group = lin / per_group;
   const int first_m = group * GROUP_M;
@@ -105,7 +137,7 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
 // separate two calls in one workgroup by a barrier (the LDS is reused).
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
           int BM, int BN, int BKT, int WM, int WN, int PADB>
-__device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn) {
+__device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool mirror) {
   typedef typename elem<T, CPLX>::type E;
   typedef typename acc_t<T>::type A4;
   constexpr int WGN = BN / (16 * WN);
@@ -267,6 +299,10 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn) {
           if (row == col) out += gam;
         }
         Cg[caddr] = out;
+        if (mirror) {
+          if constexpr (CPLX) out.im = -out.im;
+          Cg[ctr ? row * ldc + col : col * ldc + row] = out;
+        }
       }
 }
 
@@ -275,8 +311,11 @@ template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
 gemm_kernel(const Params p) {
   int tm, tn;
-  tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
-  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN, PADB>(p, tm, tn);
+  if (p.herm)
+    tri_coords(xcd_linear(blockIdx.x, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  else
+    tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, p.herm && tm != tn);
 }
 
 // Persistent grouped products: items[0 .. count) each describe one product
@@ -302,11 +341,18 @@ grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
     }
     const Params p = items[lo].p;
     const int local = t - items[lo].tile_begin;
-    const int tm = local / p.tiles_n, tn = local % p.tiles_n;
+    int tm, tn;
+    if (p.herm) {
+      tri_coords(local, p.tiles_m, tm, tn);
+    } else {
+      tm = local / p.tiles_n;
+      tn = local % p.tiles_n;
+    }
+    const bool mirror = p.herm && tm != tn;
     if (items[lo].exact)
-      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn);
+      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror);
     else
-      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN, PADB>(p, tm, tn);
+      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror);
     __syncthreads();
   }
 }
@@ -368,9 +414,12 @@ int launch_shape(const GemmDesc& d, hipStream_t s) {
   p.alpha_re = d.alpha_re; p.alpha_im = d.alpha_im;
   p.beta_re = d.beta_re; p.beta_im = d.beta_im; p.gamma = d.gamma;
   p.conj_a = d.conj_a; p.conj_b = d.conj_b; p.c_trans = d.c_trans; p.cin_trans = d.cin_trans;
+  // the triangle needs square tiles; other shapes compute every tile
+  p.herm = d.herm && S::BM == S::BN && d.M == d.N;
   p.tiles_m = int((d.M + S::BM - 1) / S::BM);
   p.tiles_n = int((d.N + S::BN - 1) / S::BN);
-  const int64_t tiles = int64_t(p.tiles_m) * p.tiles_n;
+  const int64_t tiles = p.herm ? int64_t(p.tiles_m) * (p.tiles_m + 1) / 2
+                               : int64_t(p.tiles_m) * p.tiles_n;
   if (tiles <= 0) return TC_OK;
   if (tiles > (int64_t(1) << 31) - 1) { set_error("product too large"); return TC_ERR_UNSUPPORTED; }
   const bool exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
@@ -422,6 +471,7 @@ Params make_params(const GemmDesc& d) {
   p.alpha_re = d.alpha_re; p.alpha_im = d.alpha_im;
   p.beta_re = d.beta_re; p.beta_im = d.beta_im; p.gamma = d.gamma;
   p.conj_a = d.conj_a; p.conj_b = d.conj_b; p.c_trans = d.c_trans; p.cin_trans = d.cin_trans;
+  p.herm = d.herm && S::BM == S::BN && d.M == d.N;
   p.tiles_m = int((d.M + S::BM - 1) / S::BM);
   p.tiles_n = int((d.N + S::BN - 1) / S::BN);
   return p;
@@ -440,7 +490,8 @@ int build_items(const std::vector<GemmDesc>& ds, std::vector<GroupItem>& items, 
     it.p = make_params<S>(d);
     it.tile_begin = int(t);
     it.exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
-    t += int64_t(it.p.tiles_m) * it.p.tiles_n;
+    t += it.p.herm ? int64_t(it.p.tiles_m) * (it.p.tiles_m + 1) / 2
+                   : int64_t(it.p.tiles_m) * it.p.tiles_n;
     items.push_back(it);
   }
   if (t > (int64_t(1) << 30)) { set_error("too many tiles in one group"); return TC_ERR_UNSUPPORTED; }

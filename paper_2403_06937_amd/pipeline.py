@@ -42,7 +42,7 @@ def propagator(model: Model, dt: float, method: int = TC_EXPM_SS_TAYLOR, device=
 def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: float,
            gemm_mode: int = TC_GEMM_F64, frame: int = TC_FRAME_LAB, renorm_every: int = 0,
            record_every: int = 1, checkpoint_every: int = 0, record_photons: bool = False,
-           ws=None):
+           ws=None, full_product: bool = False):
     """Steps rho (device, complex128 or complex64) in place; returns the records
     (pop [R], photon distribution [R, c+1] or None, checkpoints or None)."""
     rho_dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
@@ -55,7 +55,8 @@ def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: flo
         ck = torch.empty((steps // checkpoint_every + 1, model.N, model.N), dtype=rho.dtype,
                          device=rho.device)
     opts = make_opts(steps, dt, gemm_mode, rho_dtype, frame, renorm_every,
-                     record_every if record_every else 0, checkpoint_every)
+                     record_every if record_every else 0, checkpoint_every,
+                     full_product=int(full_product))
     inst = make_instance(model, U, rho, pop, pd, ck)
     tc_evolve([inst], opts, ws=ws, device=rho.device)
     return pop, pd, ck

@@ -45,12 +45,12 @@ def max_entry_error_pure(rho_gpu: np.ndarray, psi: np.ndarray, block=2048) -> fl
 
 
 def run_gpu(inst, dt, steps, mode=tcm.TC_GEMM_F64, frame=tcm.TC_FRAME_LAB, renorm=0,
-            rho_dtype=torch.complex128, record_every=1, checkpoint_every=0):
+            rho_dtype=torch.complex128, record_every=1, checkpoint_every=0, full=False):
     m = pipeline.model_of(inst)
     _, U = pipeline.propagator(m, dt)
     rho = _dev(np.outer(inst.psi0, inst.psi0.conj()), rho_dtype)
     pop, _, ck = pipeline.evolve(m, U, rho, steps, dt, mode, frame, renorm, record_every,
-                                 checkpoint_every)
+                                 checkpoint_every, full_product=full)
     torch.cuda.synchronize()
     return rho.cpu().numpy().astype(np.complex128), pop.cpu().numpy(), ck
 
@@ -140,8 +140,9 @@ def test_split_lab_frame_error_is_reported():
 
 
 def test_ragged_sizes_all_modes():
-    """N = 24 and 80 (not multiples of any tile) in every mode."""
-    for (n, c) in [(3, 2), (4, 4)]:
+    """N = 24, 80 and 160 (not multiples of any tile; 160 spans two tile rows,
+    so the mirrored triangle writes into the padded planes) in every mode."""
+    for (n, c) in [(3, 2), (4, 4), (5, 4)]:
         inst = ti.random_model(n, c, 7, state="gaussian")
         P = oev.SectorPropagator(n, c, inst.g, inst.omega_a)
         psiT = P.psi(inst.psi0, 30 * 0.1)
@@ -150,6 +151,42 @@ def test_ragged_sizes_all_modes():
             rdt = torch.complex128 if mode == tcm.TC_GEMM_F64 else torch.complex64
             rho, _, _ = run_gpu(inst, 0.1, 30, mode, tcm.TC_FRAME_ROTATING, rho_dtype=rdt)
             assert max_entry_error_pure(rho, psiT) < tol, (n, c, mode)
+
+
+@pytest.mark.parametrize("mode,frame,rdt,tol", [
+    (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 1e-10),
+    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_LAB, torch.complex64, 1e-3),
+])
+def test_mirrored_triangle_against_full_product(mode, frame, rdt, tol):
+    """n=8, c=4 (N=1280: 10 tile rows, two groups of tile rows, the second
+    ragged in count): the mirrored upper triangle against every tile of both
+    products and against the oracle.  Off the diagonal tiles the result is
+    Hermitian to the bit; everywhere it is as close to the oracle as the full
+    product, and the two differ by rounding only."""
+    inst = ti.random_model(8, 4, 130, state="haar2")
+    dt, steps = 0.05, 55          # 15 products after the last renormalisation
+    a, pa, _ = run_gpu(inst, dt, steps, mode, frame, renorm=20, rho_dtype=rdt)
+    b, pb, _ = run_gpu(inst, dt, steps, mode, frame, renorm=20, rho_dtype=rdt, full=True)
+    P = oev.SectorPropagator(inst.n, inst.c, inst.g, inst.omega_a)
+    psiT = P.psi(inst.psi0, steps * dt)
+    ea, eb = max_entry_error_pure(a, psiT), max_entry_error_pure(b, psiT)
+    print(f"mode={mode} frame={frame} triangle {ea:.3e} full {eb:.3e}", flush=True)
+    assert ea < tol and eb < tol
+    assert ea <= 2 * eb + 1e-15
+    N, T = a.shape[0], 128
+    off = np.ones((N, N), bool)
+    for t0 in range(0, N, T):
+        off[t0:t0 + T, t0:t0 + T] = False
+    hb = float(np.max(np.abs(b - b.conj().T)))
+    ha = float(np.max(np.abs(a - a.conj().T)))
+    if frame == tcm.TC_FRAME_LAB:
+        assert np.array_equal(a[off], a.conj().T[off])
+    # what is left sits in the diagonal tiles, of the same size as the full
+    # product's (the two runs' rounding differs, so not to the bit)
+    assert ha <= 1.5 * hb + 1e-15 or (frame != tcm.TC_FRAME_LAB and ha <= 1e-6)
+    assert float(np.max(np.abs(a - b))) < (1e-13 if mode == tcm.TC_GEMM_F64 else 2e-5)
 
 
 def test_zero_steps_and_dt_zero():
@@ -204,15 +241,18 @@ def test_bitwise_rerun_determinism():
 
 
 def test_batch_equals_single_runs():
+    """Every tile of both products (full_product = 1): the batched and single
+    runs are bitwise equal whatever tile shape each picks."""
     insts = [ti.random_model(n, c, 20 + n, state="gaussian") for (n, c) in [(3, 1), (4, 2), (5, 1)]]
     dt, steps = 0.02, 40
-    singles = [run_gpu(i, dt, steps, tcm.TC_GEMM_F32, tcm.TC_FRAME_LAB, 0, torch.complex64)
-               for i in insts]
+    singles = [run_gpu(i, dt, steps, tcm.TC_GEMM_F32, tcm.TC_FRAME_LAB, 0, torch.complex64,
+                       full=True) for i in insts]
     models = [pipeline.model_of(i) for i in insts]
     Us = [pipeline.propagator(m, dt)[1] for m in models]
     rhos = [_dev(i.rho0(), torch.complex64) for i in insts]
     pops = [torch.zeros(steps + 1, dtype=torch.float64, device=DEV) for _ in insts]
-    opts = tcm.make_opts(steps, dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_LAB, 0, 1)
+    opts = tcm.make_opts(steps, dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_LAB, 0, 1,
+                         full_product=1)
     tcm.tc_evolve([tcm.make_instance(m, U, r, p) for m, U, r, p in zip(models, Us, rhos, pops)],
                   opts)
     for k in range(3):
