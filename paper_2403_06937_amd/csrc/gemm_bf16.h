@@ -15,11 +15,17 @@ constexpr int SPLIT_BM = 128, SPLIT_BN = 128, SPLIT_BK = 32;
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// A 4-plane operand: plane p at base + p * pstride, rows of ld bf16 (K-contiguous).
+// A 4-plane operand of rows x ld bf16 per plane (K-contiguous rows, ld a
+// multiple of SPLIT_BK), the planes interleaved by 32-deep K slices: element k
+// of row r of plane q sits at base + plane_offset(ld, r, k, q), so the four
+// planes of one row's K slice are 256 contiguous bytes (two cache lines).
 struct Planes4 {
   uint16_t* base = nullptr;
-  int64_t ld = 0, rows = 0, pstride = 0;
+  int64_t ld = 0, rows = 0;
 };
+__host__ __device__ inline int64_t plane_offset(int64_t ld, int64_t r, int64_t k, int q) {
+  return r * 4 * ld + (k / SPLIT_BK) * (4 * SPLIT_BK) + q * SPLIT_BK + k % SPLIT_BK;
+}
 
 // Planes used by the split-BF16 time step of one N x N instance (padded to Np).
 struct SplitPlanes {

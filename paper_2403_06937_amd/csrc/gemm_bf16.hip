@@ -2,6 +2,8 @@
 //
 // Operands are four bfloat16 planes (Re hi, Re lo, Im hi, Im lo), each stored
 // with K contiguous: rows of A are its M rows, rows of B are its N columns.
+// The planes are interleaved by 32-deep K slices (Planes4), so the K tile of
+// one row is 256 contiguous bytes: a load covers whole cache lines.
 // For one 16 x 16 output block and a 32-deep K slice the kernel issues
 //   Re += Ar_h Br_h + Ar_h Br_l + Ar_l Br_h - Ai_h Bi_h - Ai_h Bi_l - Ai_l Bi_h
 //   Im += Ar_h Bi_h + Ar_h Bi_l + Ar_l Bi_h + Ai_h Br_h + Ai_h Br_l + Ai_l Br_h
@@ -15,11 +17,17 @@
 // Tiling: 128 x 128 outputs per workgroup, K tile 32, all eight planes
 // double-buffered in LDS (128 KB).  Default shape: 512 threads = 2 x 4 waves
 // of 64 x 32 outputs (4 x 2 blocks), two waves per SIMD, the next K tile
-// staged in registers (measured at N = 12288: 32.2 ms per product against
-// 41.6 ms for 4 waves of 64 x 64).
+// staged in registers and written to LDS at the start of the iteration after
+// its load, so that the load has a whole iteration to arrive.  Measured at
+// N = 12288 (mean of a full and a triangle launch): 21.2 ms; with the planes
+// stored one after another instead of interleaved 24.8 ms, with the store at
+// the end of the loading iteration 25.2 ms; 4 waves of 64 x 64: 29.5 ms.
+// A variant with one wave per SIMD (128 x 32 outputs each, accumulators in
+// AGPRs) that reads its B fragments straight from global memory ran at 31 ms.
 // 16-byte chunks are XOR-swizzled by row so that the 16 rows a wave reads at
 // one K offset hit distinct LDS banks.  Tile order as in the FP64 kernel:
-// XCD-contiguous ranges walked in groups of 8 tile rows.
+// XCD-contiguous ranges walked in groups of 8 tile rows; a Hermitian result
+// walks the upper tile triangle only.
 //
 // The epilogue forms alpha * acc + beta * Cin in FP32 and writes any of: the
 // FP32 result, and the hi/lo planes of the result (row-major or transposed)
@@ -57,14 +65,16 @@ __device__ __forceinline__ f4 mma(const u4& a, const u4& b, f4 c) {
 
 __device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
 
+// Plane operands are in the interleaved layout of Planes4; lda, ldb and ldp
+// are their padded K extents (the row stride is four times that).
 struct SplitParams {
-  const uint16_t* A; int64_t lda, a_ps;
-  const uint16_t* B; int64_t ldb, b_ps;
+  const uint16_t* A; int64_t lda;
+  const uint16_t* B; int64_t ldb;
   int64_t M, N, Kp;
   float ar, ai, br, bi;
   const c64* Cin; int64_t ldcin; int cin_trans;
   c64* Cf; int64_t ldcf;
-  uint16_t* P; int64_t ldp, p_ps; int p_trans;
+  uint16_t* P; int64_t ldp; int p_trans;
   int herm;   // Hermitian result (M == N): upper tile triangle, mirrored stores
   int tiles_m, tiles_n;
 };
@@ -116,18 +126,99 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
   tn = in_group / gsize;
 }
 
-// WGM x WGN waves, each owning WM x WN blocks of 16 x 16 outputs; the
-// workgroup tile is always 128 x 128 (the plane padding).  DEPTH register
-// stages carry the tiles ahead of the one being multiplied.
-template <int WGM, int WGN, int WM, int WN, int DEPTH>
+// Epilogue of one wave's WM x WN blocks of 16 x 16 outputs whose first output
+// is (r0, c0): alpha * acc + beta * Cin in FP32, then any of the FP32 result
+// and its hi/lo planes (row-major or transposed).  mirror: the tile lies above
+// the diagonal of a Hermitian result, so element (col, row) = conj(row, col)
+// is stored as well.
+template <int WM, int WN>
+__device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&acc_re)[WM][WN],
+                                               const f4 (&acc_im)[WM][WN], int64_t r0,
+                                               int64_t c0, bool mirror) {
+  const bool use_beta = p.Cin != nullptr && (p.br != 0.f || p.bi != 0.f);
+  const int lr = threadIdx.x & 15, lc = (threadIdx.x >> 4) & 3;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int64_t row0 = r0 + i * 16 + 4 * lc;
+      const int64_t col = c0 + j * 16 + lr;
+      float vr[4], vi[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + r;
+        const float xr = acc_re[i][j][r], xi = acc_im[i][j][r];
+        float yr = p.ar * xr - p.ai * xi;
+        float yi = p.ar * xi + p.ai * xr;
+        const bool inb = row < p.M && col < p.N;
+        if (use_beta && inb) {
+          const c64 c = p.cin_trans ? p.Cin[col * p.ldcin + row] : p.Cin[row * p.ldcin + col];
+          yr += p.br * c.re - p.bi * c.im;
+          yi += p.br * c.im + p.bi * c.re;
+        }
+        if (!inb) { yr = 0.f; yi = 0.f; }
+        vr[r] = yr;
+        vi[r] = yi;
+        if (p.Cf && inb) {
+          p.Cf[row * p.ldcf + col] = c64{yr, yi};
+          if (mirror) p.Cf[col * p.ldcf + row] = c64{yr, -yi};
+        }
+      }
+      if (p.P) {
+        uint16_t h[4][4];   // [plane][r]
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          split2(vr[r], h[PL_RH][r], h[PL_RL][r]);
+          split2(vi[r], h[PL_IH][r], h[PL_IL][r]);
+        }
+        // the split of -x is the negated split of x (RNE is symmetric), so the
+        // mirrored element's imaginary planes are the sign-flipped h[PL_I*]
+        const uint16_t neg[4] = {0, 0, 0x8000u, 0x8000u};
+        if (p.p_trans || mirror) {
+          const uint16_t f = p.p_trans ? 0 : 0x8000u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t m = (PL_IH == q || PL_IL == q) ? f : 0;
+            const u2 v = u2{(uint32_t(h[q][0]) | (uint32_t(h[q][1]) << 16)) ^ (m | (m << 16)),
+                            (uint32_t(h[q][2]) | (uint32_t(h[q][3]) << 16)) ^ (m | (m << 16))};
+            *reinterpret_cast<u2*>(p.P + plane_offset(p.ldp, col, row0, q)) = v;
+          }
+        }
+        if (!p.p_trans || mirror) {
+          const bool flip = p.p_trans;   // here this is the mirrored element
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              p.P[plane_offset(p.ldp, row0 + r, col, q)] = h[q][r] ^ (flip ? neg[q] : 0);
+        }
+      }
+    }
+}
+
+// Publishes this wave's LDS writes to the workgroup: waits for them, then a
+// barrier.  Outstanding global loads are not waited for (__syncthreads would
+// wait for those too); the memory clobber keeps the compiler from moving LDS
+// accesses across it.
+__device__ __forceinline__ void sync_lds() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// WGM x WGN waves, each owning WM x WN blocks of 16 x 16 outputs of a
+// 128 x 128 tile.  Both operands pass through LDS, [buf][plane][row][chunk]
+// with 16-byte chunks (4 per 32-deep row), double-buffered (128 KB).  The next
+// K tile is staged in registers: at the start of iteration t, tile t + 1 goes
+// from the registers into the LDS buffer freed by the last barrier and the
+// registers are refilled with tile t + 2 before the products, so a load has a
+// whole iteration to arrive and the barrier waits for no global load.
+template <int WGM, int WGN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const SplitParams p) {
   constexpr int NT = 64 * WGM * WGN;
   static_assert(16 * WM * WGM == SPLIT_BM && 16 * WN * WGN == SPLIT_BN, "128 x 128 tile");
   static_assert(NT == 256 || NT == 512, "staging pattern");
-  static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
-  constexpr int RPT = 512 / NT;          // rows of each plane a thread stages
-  constexpr int NST = 8 * RPT;           // 16-byte chunks staged per thread and tile
-  // [buf][plane][row][chunk]: 16-byte chunks, 4 per 32-deep row
+  // a tile of one operand is 128 rows x 256 bytes (four planes of 32 bf16):
+  // 2048 chunks; thread t moves chunk t % 16 of rows t / 16 + h NT / 16
+  constexpr int RPT = 2048 / NT;        // chunks per thread and operand
   __shared__ u4 sA[2][4][SPLIT_BM][4];
   __shared__ u4 sB[2][4][SPLIT_BN][4];
 
@@ -142,39 +233,35 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
     tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = int64_t(tm) * SPLIT_BM, n0 = int64_t(tn) * SPLIT_BN;
 
-  // Staging: per plane a 128-row x 32-deep tile is 512 chunks of 16 bytes;
-  // thread t moves chunk (t & 3) of rows (t >> 2) + h NT/4 (h < RPT) of every
-  // plane of A and B.  Pointers are formed once; each K tile adds 32 elements.
-  const int64_t lda = p.lda, ldb = p.ldb, a_ps = p.a_ps, b_ps = p.b_ps;
-  const int srow = tid >> 2, schunk = tid & 3;
+  // Each K tile of a row is 256 contiguous bytes, so a wave's load covers
+  // whole 128-byte lines.  Chunk c of a row slice holds plane c / 4, K chunk
+  // c % 4; it lands in LDS at [plane][row][(c % 4) ^ swz(row)].
+  const int64_t rsa = 4 * p.lda, rsb = 4 * p.ldb;     // row strides
+  const int srow = tid >> 4, sc = tid & 15;
+  const int sq = sc >> 2, sw = (sc & 3) ^ swz(srow);  // swz(srow + 16 h) == swz(srow)
   // workgroup-uniform bases and one 32-bit per-lane byte offset per operand
-  // (srow < 128 rows of at most 2^23 elements), so every load is a uniform
-  // base plus the same lane offset
-  const uint16_t* __restrict__ baseA = p.A + m0 * lda;
-  const uint16_t* __restrict__ baseB = p.B + n0 * ldb;
-  const uint32_t offA = uint32_t((srow * lda + schunk * 8) * 2);
-  const uint32_t offB = uint32_t((srow * ldb + schunk * 8) * 2);
-  const int sw = schunk ^ swz(srow);   // swz(srow + NT/4) == swz(srow)
-  auto load = [&](u4 (&st)[NST], int64_t kt) {
-    const int64_t k0 = kt * SPLIT_BK;
+  // (rows below 128 of at most 2^23 bf16), so each load is a uniform base plus
+  // a lane offset
+  const uint16_t* __restrict__ baseA = p.A + m0 * rsa;
+  const uint16_t* __restrict__ baseB = p.B + n0 * rsb;
+  const uint32_t offA = uint32_t((srow * rsa + sc * 8) * 2);
+  const uint32_t offB = uint32_t((srow * rsb + sc * 8) * 2);
+  auto load = [&](u4 (&st)[2 * RPT], int64_t kt) {
+    const int64_t k0 = kt * 4 * SPLIT_BK;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int h = 0; h < RPT; ++h) {
-        const char* ga = reinterpret_cast<const char*>(baseA + q * a_ps + h * (NT / 4) * lda + k0);
-        const char* gb = reinterpret_cast<const char*>(baseB + q * b_ps + h * (NT / 4) * ldb + k0);
-        st[RPT * q + h] = *reinterpret_cast<const u4*>(ga + offA);
-        st[4 * RPT + RPT * q + h] = *reinterpret_cast<const u4*>(gb + offB);
-      }
+    for (int h = 0; h < RPT; ++h) {
+      const char* ga = reinterpret_cast<const char*>(baseA + h * (NT / 16) * rsa + k0);
+      const char* gb = reinterpret_cast<const char*>(baseB + h * (NT / 16) * rsb + k0);
+      st[h] = *reinterpret_cast<const u4*>(ga + offA);
+      st[RPT + h] = *reinterpret_cast<const u4*>(gb + offB);
+    }
   };
-  auto store = [&](const u4 (&st)[NST], int buf) {
+  auto store = [&](const u4 (&st)[2 * RPT], int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int h = 0; h < RPT; ++h) {
-        sA[buf][q][srow + (NT / 4) * h][sw] = st[RPT * q + h];
-        sB[buf][q][srow + (NT / 4) * h][sw] = st[4 * RPT + RPT * q + h];
-      }
+    for (int h = 0; h < RPT; ++h) {
+      sA[buf][sq][srow + (NT / 16) * h][sw] = st[h];
+      sB[buf][sq][srow + (NT / 16) * h][sw] = st[RPT + h];
+    }
   };
 
   f4 acc_re[WM][WN], acc_im[WM][WN];
@@ -225,112 +312,31 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
     }
   };
 
-  if constexpr (DEPTH == 1) {
-    // LDS buffer t % 2 holds tile t; the register stage carries tile t + 1
-    u4 st[NST];
-    if (ktiles > 0) {
-      load(st, 0);
-      store(st, 0);
-    }
-    __syncthreads();
-    for (int64_t kt = 0; kt < ktiles; ++kt) {
-      const int buf = int(kt & 1);
-      if (kt + 1 < ktiles) load(st, kt + 1);
-      compute(buf);
-      if (kt + 1 < ktiles) store(st, buf ^ 1);
-      __syncthreads();
-    }
-  } else {
-    // LDS buffer t % 2 holds tile t; st0 / st1 carry the tiles two ahead.
-    // Each barrier both publishes the next buffer and retires the one just read.
-    u4 st0[NST], st1[NST];
-    if (ktiles > 0) {
-      load(st0, 0);
-      store(st0, 0);
-    }
-    if (ktiles > 1) load(st1, 1);
-    __syncthreads();
-    for (int64_t kt = 0; kt < ktiles; kt += 2) {
-      if (kt + 2 < ktiles) load(st0, kt + 2);
-      compute(0);
-      if (kt + 1 < ktiles) store(st1, 1);
-      __syncthreads();
-      if (kt + 1 >= ktiles) break;
-      if (kt + 3 < ktiles) load(st1, kt + 3);
-      compute(1);
-      if (kt + 2 < ktiles) store(st0, 0);
-      __syncthreads();
-    }
+  // LDS buffer t % 2 holds tile t
+  u4 st[2 * RPT];
+  if (ktiles > 0) {
+    load(st, 0);
+    store(st, 0);
+    if (ktiles > 1) load(st, 1);
+  }
+  sync_lds();
+  for (int64_t kt = 0; kt < ktiles; ++kt) {
+    if (kt + 1 < ktiles) store(st, int((kt + 1) & 1));
+    if (kt + 2 < ktiles) load(st, kt + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(int(kt & 1));
+    sync_lds();
   }
 
-  // epilogue; a mirrored tile also stores element (col, row) = conj(row, col)
-  const bool use_beta = p.Cin != nullptr && (p.br != 0.f || p.bi != 0.f);
-  const bool mirror = p.herm && tm != tn;
-#pragma unroll
-  for (int i = 0; i < WM; ++i)
-#pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      const int64_t row0 = m0 + (wm * WM + i) * 16 + 4 * lc;
-      const int64_t col = n0 + (wn * WN + j) * 16 + lr;
-      float vr[4], vi[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + r;
-        const float xr = acc_re[i][j][r], xi = acc_im[i][j][r];
-        float yr = p.ar * xr - p.ai * xi;
-        float yi = p.ar * xi + p.ai * xr;
-        const bool inb = row < p.M && col < p.N;
-        if (use_beta && inb) {
-          const c64 c = p.cin_trans ? p.Cin[col * p.ldcin + row] : p.Cin[row * p.ldcin + col];
-          yr += p.br * c.re - p.bi * c.im;
-          yi += p.br * c.im + p.bi * c.re;
-        }
-        if (!inb) { yr = 0.f; yi = 0.f; }
-        vr[r] = yr;
-        vi[r] = yi;
-        if (p.Cf && inb) {
-          p.Cf[row * p.ldcf + col] = c64{yr, yi};
-          if (mirror) p.Cf[col * p.ldcf + row] = c64{yr, -yi};
-        }
-      }
-      if (p.P) {
-        uint16_t h[4][4];   // [plane][r]
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          split2(vr[r], h[PL_RH][r], h[PL_RL][r]);
-          split2(vi[r], h[PL_IH][r], h[PL_IL][r]);
-        }
-        // the split of -x is the negated split of x (RNE is symmetric), so the
-        // mirrored element's imaginary planes are the sign-flipped h[PL_I*]
-        const uint16_t neg[4] = {0, 0, 0x8000u, 0x8000u};
-        if (p.p_trans || mirror) {
-          const uint16_t f = p.p_trans ? 0 : 0x8000u;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const uint32_t m = (PL_IH == q || PL_IL == q) ? f : 0;
-            const u2 v = u2{(uint32_t(h[q][0]) | (uint32_t(h[q][1]) << 16)) ^ (m | (m << 16)),
-                            (uint32_t(h[q][2]) | (uint32_t(h[q][3]) << 16)) ^ (m | (m << 16))};
-            *reinterpret_cast<u2*>(p.P + q * p.p_ps + col * p.ldp + row0) = v;
-          }
-        }
-        if (!p.p_trans || mirror) {
-          const bool flip = p.p_trans;   // here this is the mirrored element
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              p.P[q * p.p_ps + (row0 + r) * p.ldp + col] = h[q][r] ^ (flip ? neg[q] : 0);
-        }
-      }
-    }
+  split_epilogue<WM, WN>(p, acc_re, acc_im, m0 + wm * WM * 16, n0 + wn * WN * 16,
+                         p.herm && tm != tn);
 }
 
 // out(r, c) for r < Rp, c < Cp from src (R x C valid, element (r, c) at
 // src[r*ld + c], or src[c*ld + r] when trans), conjugated if conj, zero outside.
 constexpr int ST = 32;
 __global__ void split_matrix_kernel(const c64* __restrict__ src, int64_t ld, int64_t R, int64_t C,
-                                    int trans, int conj, uint16_t* __restrict__ P, int64_t ldp,
-                                    int64_t ps) {
+                                    int trans, int conj, uint16_t* __restrict__ P, int64_t ldp) {
   __shared__ float2 tile[ST][ST + 1];
   const int tx = threadIdx.x % ST, ty = threadIdx.x / ST;   // 32 x 8
   const int64_t r0 = int64_t(blockIdx.y) * ST, c0 = int64_t(blockIdx.x) * ST;
@@ -353,11 +359,10 @@ __global__ void split_matrix_kernel(const c64* __restrict__ src, int64_t ld, int
     uint16_t rh, rl, ih, il;
     split2(v.x, rh, rl);
     split2(conj ? -v.y : v.y, ih, il);
-    const int64_t o = r * ldp + c;
-    P[0 * ps + o] = rh;
-    P[1 * ps + o] = rl;
-    P[2 * ps + o] = ih;
-    P[3 * ps + o] = il;
+    P[plane_offset(ldp, r, c, PL_RH)] = rh;
+    P[plane_offset(ldp, r, c, PL_RL)] = rl;
+    P[plane_offset(ldp, r, c, PL_IH)] = ih;
+    P[plane_offset(ldp, r, c, PL_IL)] = il;
   }
 }
 
@@ -365,7 +370,6 @@ Planes4 take_planes(Arena& ar, int64_t rows, int64_t ld) {
   Planes4 p;
   p.rows = rows;
   p.ld = ld;
-  p.pstride = rows * ld;
   p.base = static_cast<uint16_t*>(ar.take(size_t(4) * size_t(rows) * size_t(ld) * 2));
   return p;
 }
@@ -375,18 +379,17 @@ int split_into(const c64* src, int64_t ld, int64_t R, int64_t C, bool trans, boo
   // fills all P.rows x P.ld entries (padding becomes zero)
   dim3 grid(unsigned(P.ld / ST), unsigned(P.rows / ST));
   hipLaunchKernelGGL(split_matrix_kernel, grid, dim3(256), 0, s, src, ld, R, C, int(trans),
-                     int(conj), P.base, P.ld, P.pstride);
+                     int(conj), P.base, P.ld);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
 
-// Kernel shape: 0 = 4 waves of 64 x 64, one register stage; 1 = 8 waves of
-// 64 x 32, two stages; 2 = 8 waves of 64 x 32, one stage; 3 = 8 waves of
-// 32 x 64, two stages.  TC_SPLIT_VARIANT overrides the default for timing.
+// Kernel shape: 0 = 8 waves of 64 x 32 outputs (default), 1 = 4 waves of
+// 64 x 64.  TC_SPLIT_VARIANT selects one for timing.
 int split_variant() {
   static const int v = [] {
     const char* e = getenv("TC_SPLIT_VARIANT");
-    return e ? atoi(e) : 2;
+    return e ? atoi(e) : 0;
   }();
   return v;
 }
@@ -395,13 +398,13 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
               float ai, float br, float bi, const c64* Cin, int64_t ldcin, bool cin_trans, c64* Cf,
               int64_t ldcf, const Planes4* P, bool p_trans, bool herm, hipStream_t s) {
   SplitParams q;
-  q.A = A.base; q.lda = A.ld; q.a_ps = A.pstride;
-  q.B = B.base; q.ldb = B.ld; q.b_ps = B.pstride;
+  q.A = A.base; q.lda = A.ld;
+  q.B = B.base; q.ldb = B.ld;
   q.M = M; q.N = N; q.Kp = Kp;
   q.ar = ar; q.ai = ai; q.br = br; q.bi = bi;
   q.Cin = Cin; q.ldcin = ldcin; q.cin_trans = cin_trans;
   q.Cf = Cf; q.ldcf = ldcf;
-  q.P = P ? P->base : nullptr; q.ldp = P ? P->ld : 0; q.p_ps = P ? P->pstride : 0;
+  q.P = P ? P->base : nullptr; q.ldp = P ? P->ld : 0;
   q.p_trans = p_trans;
   q.herm = herm;
   q.tiles_m = int((M + SPLIT_BM - 1) / SPLIT_BM);
@@ -425,12 +428,10 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
   }
   ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
   const dim3 grid{unsigned(tiles), 1u, 1u};
-  switch (split_variant()) {
-    case 1: hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, 2>), grid, dim3(512), 0, s, q); break;
-    case 2: hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, 1>), grid, dim3(512), 0, s, q); break;
-    case 3: hipLaunchKernelGGL((split_gemm_kernel<4, 2, 2, 4, 2>), grid, dim3(512), 0, s, q); break;
-    default: hipLaunchKernelGGL((split_gemm_kernel<2, 2, 4, 4, 1>), grid, dim3(256), 0, s, q); break;
-  }
+  if (split_variant() == 1)
+    hipLaunchKernelGGL((split_gemm_kernel<2, 2, 4, 4>), grid, dim3(256), 0, s, q);
+  else
+    hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2>), grid, dim3(512), 0, s, q);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -451,7 +452,7 @@ int split_operand(const c64* op, int64_t ld, int64_t N, const SplitPlanes& p, hi
   TC_RETURN_IF(split_into(op, ld, N, N, false, false, p.opA, s));
   TC_RETURN_IF(split_into(op, ld, N, N, true, true, p.opB, s));
   // X planes: their padding must be zero before the first product writes them
-  TC_TRY_HIP(hipMemsetAsync(p.X.base, 0, size_t(4) * p.X.pstride * 2, s));
+  TC_TRY_HIP(hipMemsetAsync(p.X.base, 0, size_t(4) * p.X.rows * p.X.ld * 2, s));
   return TC_OK;
 }
 
@@ -492,8 +493,8 @@ int split_gemm(const GemmDesc& d, const SplitGemmPlan& p, hipStream_t s) {
     // B plane row n, column k = op(B)(k, n) = B[k*ldb + n] when b_kmaj: transposed read
     TC_RETURN_IF(split_into(B, d.ldb, d.N, d.K, d.b_kmaj, d.conj_b, p.B, s));
   } else {
-    TC_TRY_HIP(hipMemsetAsync(p.A.base, 0, size_t(4) * p.A.pstride * 2, s));
-    TC_TRY_HIP(hipMemsetAsync(p.B.base, 0, size_t(4) * p.B.pstride * 2, s));
+    TC_TRY_HIP(hipMemsetAsync(p.A.base, 0, size_t(4) * p.A.rows * p.A.ld * 2, s));
+    TC_TRY_HIP(hipMemsetAsync(p.B.base, 0, size_t(4) * p.B.rows * p.B.ld * 2, s));
   }
   return run_split(p.A, p.B, d.M, d.N, p.A.ld, float(d.alpha_re), float(d.alpha_im),
                    float(d.beta_re), float(d.beta_im), static_cast<const c64*>(d.Cin), d.ldcin,
