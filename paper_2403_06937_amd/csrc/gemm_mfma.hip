@@ -78,9 +78,11 @@ constexpr int GROUP_M = 8;
 
 // Default tile variant per element type for the step / exponential layout,
 // chosen by timing every variant at N = 12288 on gfx950:
-//   complex FP64: 128x128 tiles, 8 waves, K tile 16 (240 ms per product;
-//                 64x64: 285 ms; 128x128 with K tile 8: 294 ms; 128x64: 438 ms;
-//                 LDS row padding of 0, 16 or 32 bytes: no difference)
+//   complex FP64: 128x128 tiles, 8 waves, K tile 16 (240 ms per full
+//                 product before the staged tile was stored early, 231 ms
+//                 after; 64x64: 285 ms; 128x128 with K tile 8: 294 ms;
+//                 128x64: 438 ms; LDS row padding of 0, 16 or 32 bytes: no
+//                 difference)
 //   real FP64:    128x128 tiles, 8 waves (U formation 1.07 s; 128x64: 1.42 s)
 //   complex FP32: 128x128 tiles, 8 waves (112 ms; 128x64: 118 ms)
 template <typename T, bool CPLX> struct DefaultVariant { static constexpr int value = 1; };
@@ -118,6 +120,14 @@ __device__ __forceinline__ void tri_coords(int lin, int T, int& tm, int& tn) {
     lin -= cnt;
     first += gs;
   }
+}
+
+// Publishes this wave's LDS writes to the workgroup: waits for them, then a
+// barrier.  Outstanding global loads are not waited for (__syncthreads would
+// wait for those too); the memory clobber keeps the compiler from moving LDS
+// accesses across it.
+__device__ __forceinline__ void sync_lds() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // Tile coordinates of this workgroup (XCD-contiguous, grouped ordering).
@@ -226,17 +236,24 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
     for (int j = 0; j < B_PT; ++j) sB[buf][kb + j * dkb][nb + j * dnb] = rb[j];
   };
 
+  // LDS buffer t % 2 holds K tile t.  The registers carry tile t + 1 into the
+  // other buffer at the start of iteration t (free since the last barrier)
+  // and are refilled with tile t + 2 before the products, so a load has a
+  // whole iteration to arrive and the barrier waits for no global load.
   if (ktiles > 0) {
     load_tiles(0);
     store_tiles(0);
+    if (ktiles > 1) load_tiles(1);
   }
-  __syncthreads();
+  sync_lds();
 
   const int lrow = lane >> 4;   // k offset within the 4-deep slice
   const int lcol = lane & 15;   // m / n offset within the 16-wide block
   for (int64_t kt = 0; kt < ktiles; ++kt) {
     const int buf = int(kt & 1);
-    if (kt + 1 < ktiles) load_tiles(kt + 1);
+    if (kt + 1 < ktiles) store_tiles(buf ^ 1);
+    if (kt + 2 < ktiles) load_tiles(kt + 2);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k4 = 0; k4 < BKT / 4; ++k4) {
       E a[WM], b[WN];
@@ -258,8 +275,7 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
           }
         }
     }
-    if (kt + 1 < ktiles) store_tiles(buf ^ 1);
-    __syncthreads();
+    sync_lds();
   }
 
   // Epilogue: C = alpha * acc + beta * Cin + gamma * [m == n]
