@@ -198,9 +198,10 @@ def bench_grad8(tcm, pipeline, ti):
             "backward_over_forward": bwd / fwd, "loss": float(loss.item())}
 
 
-def cpu_baseline(U_np, rho_np, target_s=12.0):
+def cpu_baseline(U_np, rho_np, target_s=15.0):
     """The oracle's dense step (U rho U^dag with numpy products) on a row slab of
-    the same N = 12288 matrices, timed on the host cores; scaled to steps/s."""
+    the same N = 12288 matrices, timed on the host cores; scaled to steps/s.
+    Small slabs size the final one to about target_s seconds of CPU work."""
     import numpy as np
     from oracle import linalg as olin
     try:
@@ -209,17 +210,21 @@ def cpu_baseline(U_np, rho_np, target_s=12.0):
     except Exception:
         cores = os.cpu_count()
     N = U_np.shape[0]
-    rows = 64
-    elapsed = 0.0
-    while True:
-        Ub = U_np[:rows]
+
+    def run(rows):
         t0 = time.perf_counter()
-        X = olin.gemm(Ub, rho_np)                   # rows x N
+        X = olin.gemm(U_np[:rows], rho_np)          # rows x N
         olin.gemm(X, U_np, op_b="h")                # rows x N of U rho U^dag
-        elapsed = time.perf_counter() - t0
-        if elapsed > target_s / 4 or rows >= N:
-            break
+        return time.perf_counter() - t0
+
+    rows = 64
+    elapsed = run(rows)
+    while elapsed < 1.0 and rows < N:
         rows = min(N, rows * 4)
+        elapsed = run(rows)
+    if rows < N:
+        rows = int(min(N, max(rows, rows * target_s / elapsed // 64 * 64)))
+        elapsed = run(rows)
     per_step = elapsed * N / rows
     return {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
             "sample": f"rows 0..{rows - 1} of one N={N} step (U[rows] rho U^dag, numpy/OpenBLAS "

@@ -84,11 +84,13 @@ int cgemm(bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj, bool con
   return f64 ? gemm_f64(d, s) : gemm_f32(d, s);
 }
 
-// C = op(A) op(B) + Cin in the sweep precision (Cin must not alias C).
+// C = op(A) op(B) + Cin in the sweep precision (Cin must not alias C); herm:
+// C is Hermitian, so only its upper tile triangle is multiplied and mirrored.
 int cgemm_in(bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj, bool conj_a,
              const void* B, int64_t ldb, bool b_kmaj, bool conj_b, void* C, int64_t ldc,
-             const void* Cin, hipStream_t s) {
+             const void* Cin, hipStream_t s, bool herm = false) {
   GemmDesc d;
+  d.herm = herm;
   d.M = d.N = d.K = N;
   d.A = A; d.lda = lda; d.a_kmaj = a_kmaj; d.conj_a = conj_a;
   d.B = B; d.ldb = ldb; d.b_kmaj = b_kmaj; d.conj_b = conj_b;
@@ -210,6 +212,7 @@ int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc
     g2.A = L.X; g2.lda = N; g2.a_kmaj = false;
     g2.B = L.D; g2.ldb = N; g2.b_kmaj = true; g2.conj_b = true;
     g2.C = dst; g2.ldc = N; g2.Cin = L.X; g2.ldcin = N; g2.beta_re = 1.0;
+    g2.herm = true;   // the state after the step is Hermitian
     TC_RETURN_IF(f64 ? gemm_f64(g1, s) : gemm_f32(g1, s));
     return f64 ? gemm_f64(g2, s) : gemm_f32(g2, s);
   };
@@ -269,8 +272,9 @@ int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc
         TC_RETURN_IF(cgemm(false, N, rho_prev, N, false, false, L.Y, N, true, false, L.T, N, 1.0, 0.0, s));
         TC_RETURN_IF(launch_accumulate_c64(static_cast<const c64*>(L.T), N, L.M, N, N, s));
       }
-      // O_{s-1} = Y U~ = Y + Y D
-      TC_RETURN_IF(cgemm_in(f64, N, L.Y, N, false, false, L.D, N, true, false, L.O, N, L.Y, s));
+      // O_{s-1} = Y U~ = Y + Y D, Hermitian (= U~^dag O_s U~)
+      TC_RETURN_IF(cgemm_in(f64, N, L.Y, N, false, false, L.D, N, true, false, L.O, N, L.Y, s,
+                            true));
     }
   }
   if (S == 0 && loss_out) {
