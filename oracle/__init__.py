@@ -19,4 +19,6 @@ Modules
   gradient     d(final excitation)/d(g_i, delta_i) by the Daleckii-Krein
                formula and by central finite differences
   linalg       plain matrix-product definitions used for kernel-level checks
+  open_system  the Lindblad term of Eq. (5) restored: Liouvillian, exact
+               damping channels, and the split step rho <- exp(dt L)(U rho U^dag)
 """
