@@ -79,13 +79,22 @@ typedef struct { float re, im; } tc_c64;
 /* Observable of tc_evolve_backward. */
 #define TC_OBS_EXCITED_TOTAL 0   /* L = sum_i <s_i^+ s_i^-> at the final step          */
 
-/* Model of Eq. (4). */
+/* Model of Eq. (4), with the Lindblad term of Eq. (5), which the paper sets
+ * to zero, read as cavity leakage and atomic emission at zero temperature:
+ *   L(rho) = kappa D[a] rho + gamma sum_i D[s_i^-] rho,
+ *   D[A] rho = A rho A^dag - (A^dag A rho + rho A^dag A) / 2.
+ * With kappa = gamma = 0 (the paper's case) every step is Eq. (6).  Otherwise
+ * tc_evolve follows each unitary step by exp(dt L), applied exactly as one
+ * amplitude-damping channel per atom (p = 1 - e^{-gamma dt}) and one for the
+ * cavity (eta = e^{-kappa dt}); the splitting is first order in dt. */
 typedef struct {
   int32_t n_atoms;          /* n >= 1                                               */
   int32_t photon_cutoff;    /* c >= 0: photon numbers 0..c, a^dag|c> = 0            */
   double  omega_c;          /* cavity frequency                                     */
   const double* omega_a;    /* host [n]: atomic frequencies 1 + delta_i             */
   const double* g;          /* host [n]: real couplings g_i                         */
+  double  kappa;            /* cavity leakage rate >= 0 (read by tc_evolve only)     */
+  double  gamma;            /* atomic emission rate >= 0 (read by tc_evolve only)    */
 } tc_model;
 
 /* ---------------------------------------------------------------- helpers */

@@ -71,7 +71,8 @@ class tc_c128(ctypes.Structure):
 class tc_model(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int32), ("photon_cutoff", ctypes.c_int32),
                 ("omega_c", ctypes.c_double), ("omega_a", ctypes.POINTER(ctypes.c_double)),
-                ("g", ctypes.POINTER(ctypes.c_double))]
+                ("g", ctypes.POINTER(ctypes.c_double)), ("kappa", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
 
 
 class tc_instance(ctypes.Structure):
@@ -168,13 +169,16 @@ class Model:
     g: Sequence[float]
     omega_a: Sequence[float]
     omega_c: float = 1.0
+    kappa: float = 0.0            # cavity leakage rate of the Lindblad term
+    gamma: float = 0.0            # atomic emission rate of the Lindblad term
 
     def __post_init__(self):
         self._g = np.ascontiguousarray(self.g, dtype=np.float64)
         self._wa = np.ascontiguousarray(self.omega_a, dtype=np.float64)
         self._s = tc_model(self.n, self.c, float(self.omega_c),
                            self._wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                           self._g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                           self._g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           float(self.kappa), float(self.gamma))
 
     @property
     def N(self) -> int:

@@ -28,6 +28,10 @@ int make_model_args(const tc_model* m, ModelArgs* out) {
   out->N = N;
   out->omega_c = m->omega_c;
   TC_CHECK_ARG(std::isfinite(m->omega_c), "omega_c not finite");
+  TC_CHECK_ARG(std::isfinite(m->kappa) && m->kappa >= 0.0, "kappa must be finite and >= 0");
+  TC_CHECK_ARG(std::isfinite(m->gamma) && m->gamma >= 0.0, "gamma must be finite and >= 0");
+  out->kappa = m->kappa;
+  out->gamma = m->gamma;
   for (int i = 0; i < TC_MAX_ATOMS; ++i) {
     out->omega_a[i] = i < m->n_atoms ? m->omega_a[i] : 0.0;
     out->g[i] = i < m->n_atoms ? m->g[i] : 0.0;

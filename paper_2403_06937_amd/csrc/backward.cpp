@@ -131,6 +131,10 @@ int tc_evolve_backward_workspace_size(const tc_model* m, int64_t N, const tc_evo
   ModelArgs a;
   TC_RETURN_IF(make_model_args(m, &a));
   TC_CHECK_ARG(N == a.N, "N != (c+1) 2^n");
+  if (a.kappa != 0.0 || a.gamma != 0.0) {
+    set_error("tc_evolve_backward: the adjoint covers the unitary step only (kappa = gamma = 0)");
+    return TC_ERR_UNSUPPORTED;
+  }
   TC_CHECK_ARG(o->steps >= 0, "steps < 0");
   TC_CHECK_ARG(o->checkpoint_every >= 1, "checkpoint_every must be >= 1");
   TC_CHECK_ARG(o->gemm_mode == TC_GEMM_F64 || o->gemm_mode == TC_GEMM_F32 ||

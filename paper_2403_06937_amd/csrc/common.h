@@ -60,6 +60,7 @@ struct ModelArgs {
   double omega_c;
   double omega_a[TC_MAX_ATOMS];
   double g[TC_MAX_ATOMS];
+  double kappa, gamma;   // dissipation rates of the Lindblad term (0: unitary)
 };
 
 int make_model_args(const tc_model* m, ModelArgs* out);

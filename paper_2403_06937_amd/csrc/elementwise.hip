@@ -157,6 +157,101 @@ __global__ void frame_phase_kernel(ModelArgs m, E* __restrict__ rho, int64_t ld,
   }
 }
 
+// ------------------------------------------------------- dissipation
+// Amplitude damping of the atoms on index bits b0 and b1 (b1 < 0: b0 only;
+// atom i is bit n - 1 - i), probability p = 1 - e^{-gamma dt}, f = sqrt(1 - p).
+// For one atom and the 2 x 2 block of rows {r, r + e} and columns {s, s + e}
+// (both with the atom's bit clear) the channel K0 . K0^dag + K1 . K1^dag is
+//   x00 <- x00 + p x11,  x01 <- f x01,  x10 <- f x10,  x11 <- (1 - p) x11.
+// A thread owns the (2^k x 2^k) block over the k bits of the pass, so the
+// update is in place with no other thread touching its elements.
+__device__ __forceinline__ int64_t insert_zero_bit(int64_t q, int b) {
+  return ((q >> b) << (b + 1)) | (q & ((int64_t(1) << b) - 1));
+}
+
+template <typename E, int K>
+__global__ void damp_atoms_kernel(E* __restrict__ rho, int64_t ld, int64_t N, int b0, int b1,
+                                  double p, double f) {
+  constexpr int B = 1 << K;
+  const int64_t R = N >> K;                  // reduced row / column count
+  const int64_t qs = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (qs >= R) return;
+  int64_t s0 = insert_zero_bit(qs, b0);
+  if (K == 2) s0 = insert_zero_bit(s0, b1);
+  const int64_t e[2] = {int64_t(1) << b0, K == 2 ? int64_t(1) << b1 : 0};
+  for (int64_t qr = blockIdx.y; qr < R; qr += gridDim.y) {
+    int64_t r0 = insert_zero_bit(qr, b0);
+    if (K == 2) r0 = insert_zero_bit(r0, b1);
+    double xr[B][B], xi[B][B];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int v = 0; v < B; ++v) {
+        const int64_t r = r0 + ((u & 1) ? e[0] : 0) + ((u & 2) ? e[1] : 0);
+        const int64_t c = s0 + ((v & 1) ? e[0] : 0) + ((v & 2) ? e[1] : 0);
+        const E x = rho[r * ld + c];
+        xr[u][v] = double(x.re);
+        xi[u][v] = double(x.im);
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int bit = 1 << k;
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int v = 0; v < B; ++v) {
+          if ((u & bit) || (v & bit)) continue;
+          const int u1 = u | bit, v1 = v | bit;
+          xr[u][v] += p * xr[u1][v1];
+          xi[u][v] += p * xi[u1][v1];
+          xr[u][v1] *= f; xi[u][v1] *= f;
+          xr[u1][v] *= f; xi[u1][v] *= f;
+          xr[u1][v1] *= 1.0 - p; xi[u1][v1] *= 1.0 - p;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int v = 0; v < B; ++v) {
+        const int64_t r = r0 + ((u & 1) ? e[0] : 0) + ((u & 2) ? e[1] : 0);
+        const int64_t c = s0 + ((v & 1) ? e[0] : 0) + ((v & 2) ? e[1] : 0);
+        rho[r * ld + c] = E{decltype(E::re)(xr[u][v]), decltype(E::re)(xi[u][v])};
+      }
+  }
+}
+
+// Cavity damping with eta = e^{-kappa dt}: Kraus operators
+// E_l = sum_m sqrt(binom(m, l)) eta^{(m-l)/2} (1 - eta)^{l/2} |m - l><m|, so
+//   rho'[(m,a),(m',a')] = sum_{l >= 0} sqrt(binom(m+l, l) binom(m'+l, l))
+//                         eta^{(m+m')/2} (1 - eta)^l rho[(m+l,a),(m'+l,a')].
+// A thread owns one chain (a, a', m' - m = d) and walks it from the lowest
+// photon numbers up, so each new value reads only entries not yet rewritten.
+template <typename E>
+__global__ void damp_cavity_kernel(E* __restrict__ rho, int64_t ld, int n, int c, double eta) {
+  const int64_t per = int64_t(1) << n;
+  const int64_t ac = int64_t(blockIdx.x) * TPB + threadIdx.x;   // column atom index a'
+  if (ac >= per) return;
+  const int d = int(blockIdx.z) - c;                             // m' - m
+  const int mlo = d < 0 ? -d : 0;
+  const int len = c + 1 - (d < 0 ? -d : d);
+  const double q = 1.0 - eta;
+  for (int64_t ar = blockIdx.y; ar < per; ar += gridDim.y) {
+    for (int j = 0; j < len; ++j) {
+      const int m = mlo + j, mp = m + d;
+      double coef = pow(eta, 0.5 * double(m + mp));
+      double yr = 0.0, yi = 0.0;
+      for (int l = 0; j + l < len; ++l) {
+        if (l > 0) coef *= sqrt(double(m + l) * double(mp + l)) / double(l) * q;
+        const E x = rho[(int64_t(m + l) * per + ar) * ld + int64_t(mp + l) * per + ac];
+        yr += coef * double(x.re);
+        yi += coef * double(x.im);
+      }
+      rho[(int64_t(m) * per + ar) * ld + int64_t(mp) * per + ac] =
+          E{decltype(E::re)(yr), decltype(E::re)(yi)};
+    }
+  }
+}
+
 // ------------------------------------------------------- per-step readout
 template <typename E>
 __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t ld,
@@ -594,6 +689,44 @@ int launch_frame_phase_c64(const ModelArgs& m, c64* rho, int64_t ld, double t, h
   hipLaunchKernelGGL(frame_phase_kernel<c64>, grid2(m.N, m.N), dim3(TPB), 0, s, m, rho, ld, t);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
+}
+
+template <typename E>
+int launch_dissipation_t(const ModelArgs& m, E* rho, int64_t ld, double dt, hipStream_t s) {
+  if (m.N == 0) return TC_OK;
+  if (m.gamma > 0.0) {
+    const double p = -expm1(-m.gamma * dt);        // 1 - e^{-gamma dt}
+    const double f = sqrt(1.0 - p);
+    for (int b = 0; b < m.n; b += 2) {
+      if (b + 1 < m.n) {
+        const int64_t R = m.N >> 2;
+        hipLaunchKernelGGL((damp_atoms_kernel<E, 2>), grid2(R, R), dim3(TPB), 0, s, rho, ld, m.N,
+                           b, b + 1, p, f);
+      } else {
+        const int64_t R = m.N >> 1;
+        hipLaunchKernelGGL((damp_atoms_kernel<E, 1>), grid2(R, R), dim3(TPB), 0, s, rho, ld, m.N,
+                           b, -1, p, f);
+      }
+      TC_TRY_HIP(hipGetLastError());
+    }
+  }
+  if (m.kappa > 0.0 && m.c > 0) {
+    const int64_t per = int64_t(1) << m.n;
+    const dim3 grid(unsigned((per + TPB - 1) / TPB), unsigned(per < 4096 ? per : 4096),
+                    unsigned(2 * m.c + 1));
+    hipLaunchKernelGGL(damp_cavity_kernel<E>, grid, dim3(TPB), 0, s, rho, ld, m.n, m.c,
+                       exp(-m.kappa * dt));
+    TC_TRY_HIP(hipGetLastError());
+  }
+  return TC_OK;
+}
+
+int launch_dissipation_c128(const ModelArgs& m, c128* rho, int64_t ld, double dt, hipStream_t s) {
+  return launch_dissipation_t(m, rho, ld, dt, s);
+}
+
+int launch_dissipation_c64(const ModelArgs& m, c64* rho, int64_t ld, double dt, hipStream_t s) {
+  return launch_dissipation_t(m, rho, ld, dt, s);
 }
 
 int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,

@@ -99,6 +99,18 @@ int readout(const InstPlan& p, const tc_evolve_opts& o, double* pop, double* pdi
   return launch_readout_c64(p.m, static_cast<const c64*>(p.rho), p.ldr, pop, pdist, s);
 }
 
+// exp(dt L) after a unitary step when the model has a Lindblad term; in the
+// split form the next step's rho^T planes are re-split from the damped master.
+int dissipate(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (!(p.m.kappa > 0.0 || p.m.gamma > 0.0)) return TC_OK;
+  if (o.gemm_mode == TC_GEMM_F64)
+    return launch_dissipation_c128(p.m, static_cast<c128*>(p.rho), p.ldr, o.dt, s);
+  TC_RETURN_IF(launch_dissipation_c64(p.m, static_cast<c64*>(p.rho), p.ldr, o.dt, s));
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
+    TC_RETURN_IF(split_state(static_cast<const c64*>(p.rho), p.ldr, p.N, p.planes, s));
+  return TC_OK;
+}
+
 int renorm(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_renorm_c128(static_cast<c128*>(p.rho), p.ldr, p.N, p.scratch, s);
@@ -219,6 +231,7 @@ int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipS
   if (in.checkpoints) TC_RETURN_IF(copy_checkpoint(p, in, o, 0, 0.0, s));
   for (int64_t st = 1; st <= o.steps; ++st) {
     TC_RETURN_IF(step(p, o, s));
+    TC_RETURN_IF(dissipate(p, o, s));
     if (o.renorm_every > 0 && st % o.renorm_every == 0) TC_RETURN_IF(renorm(p, o, s));
     if (rec && st % o.record_every == 0) {
       const int64_t r = st / o.record_every;
@@ -321,6 +334,7 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
   auto one_step = [&](int64_t st, hipStream_t q) -> int {
     for (int v = 1; v <= 2; ++v) TC_RETURN_IF(grouped_run(G1[v], q));
     for (int v = 1; v <= 2; ++v) TC_RETURN_IF(grouped_run(G2[v], q));
+    for (int b = 0; b < count; ++b) TC_RETURN_IF(dissipate(plans[b], o, q));
     if (o.renorm_every > 0 && st % o.renorm_every == 0)
       for (int b = 0; b < count; ++b) TC_RETURN_IF(renorm(plans[b], o, q));
     if (rec && st % o.record_every == 0) {

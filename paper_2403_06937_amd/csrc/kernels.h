@@ -36,6 +36,13 @@ int launch_rotating_d_c64(const ModelArgs& m, const c128* U, int64_t ldu, double
 int launch_frame_phase_c128(const ModelArgs& m, c128* rho, int64_t ld, double t, hipStream_t s);
 int launch_frame_phase_c64(const ModelArgs& m, c64* rho, int64_t ld, double t, hipStream_t s);
 
+// Dissipation over dt, exp(dt L) for the Lindblad term of the model (in
+// place; no-op when kappa = gamma = 0): one amplitude-damping channel per atom,
+// two atoms per pass, then the cavity channel.  Commutes with the rotating
+// frame's phase, so it applies in either frame.
+int launch_dissipation_c128(const ModelArgs& m, c128* rho, int64_t ld, double dt, hipStream_t s);
+int launch_dissipation_c64(const ModelArgs& m, c64* rho, int64_t ld, double dt, hipStream_t s);
+
 // Per-step readout of the diagonal: pop[r] = sum_s |l(s)| Re rho_ss and, if
 // pdist != NULL, pdist[r*(c+1) + m] = sum_{photon(s) = m} Re rho_ss.
 int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,

@@ -16,9 +16,11 @@ from . import (Model, TC_C128, TC_C64, TC_EXPM_SS_TAYLOR, TC_FRAME_LAB, TC_GEMM_
 
 
 def model_of(inst) -> Model:
-    """Model from an object with n, c, g, omega_a, omega_c attributes."""
+    """Model from an object with n, c, g, omega_a (and optionally omega_c, kappa,
+    gamma) attributes."""
     return Model(int(inst.n), int(inst.c), list(map(float, inst.g)),
-                 list(map(float, inst.omega_a)), float(getattr(inst, "omega_c", 1.0)))
+                 list(map(float, inst.omega_a)), float(getattr(inst, "omega_c", 1.0)),
+                 float(getattr(inst, "kappa", 0.0)), float(getattr(inst, "gamma", 0.0)))
 
 
 def hamiltonian(model: Model, device="cuda") -> torch.Tensor:

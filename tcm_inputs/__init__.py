@@ -51,6 +51,8 @@ class Instance:
     omega_a: np.ndarray           # [n] atomic frequencies 1 + delta_i
     omega_c: float = 1.0          # cavity frequency
     psi0: Optional[np.ndarray] = None   # [N] complex128, unit norm
+    kappa: float = 0.0            # cavity leakage rate (Lindblad term)
+    gamma: float = 0.0            # atomic emission rate (Lindblad term)
 
     @property
     def N(self) -> int:

@@ -131,3 +131,32 @@ def test_workspace_sizes_scale():
     assert 3.9 < b / a < 4.1
     assert tcm.tc_gemm_workspace_size(64, 64, 64, tcm.TC_GEMM_F64) == 0
     assert tcm.tc_gemm_workspace_size(64, 64, 64, tcm.TC_GEMM_SPLIT_BF16) > 0
+
+
+def test_dissipation_rates_checked_before_device_work():
+    """Negative or non-finite kappa / gamma are argument errors; the adjoint
+    rejects a model with a Lindblad term (it covers the unitary step only)."""
+    class Fake:
+        def __init__(self, p, ld):
+            self.p, self.ld = p, ld
+
+        def data_ptr(self):
+            return self.p
+
+        def stride(self, i):
+            return self.ld
+
+    for kappa, gamma in [(-0.1, 0.0), (0.0, -1e-3), (float("nan"), 0.0), (0.0, float("inf"))]:
+        m = tcm.Model(2, 1, [0.01, 0.02], [1.0, 1.0], kappa=kappa, gamma=gamma)
+        inst = tcm.make_instance(m, Fake(0x1000, m.N), Fake(0x2000, m.N))
+        with pytest.raises(tcm.TcmError) as e:
+            tcm.tc_evolve_workspace_size([inst], tcm.make_opts(10, 0.1))
+        assert e.value.code == tcm.TC_ERR_INVALID_ARGUMENT
+    ok = tcm.Model(2, 1, [0.01, 0.02], [1.0, 1.0], kappa=0.1, gamma=0.2)
+    inst = tcm.make_instance(ok, Fake(0x1000, ok.N), Fake(0x2000, ok.N))
+    assert tcm.tc_evolve_workspace_size([inst], tcm.make_opts(10, 0.1)) > 0
+    sz = ctypes.c_size_t()
+    opts = tcm.make_opts(10, 0.1, checkpoint_every=5)
+    rc = tcm.lib().tc_evolve_backward_workspace_size(ctypes.byref(ok.struct), ok.N,
+                                                     ctypes.byref(opts), ctypes.byref(sz))
+    assert rc == tcm.TC_ERR_UNSUPPORTED
