@@ -198,6 +198,37 @@ def bench_grad8(tcm, pipeline, ti):
             "backward_over_forward": bwd / fwd, "loss": float(loss.item())}
 
 
+def bench_open11(tcm, pipeline, ti, steps=20):
+    """The N = 12288 workload with the Lindblad term of Eq. (5) switched on
+    (kappa = 0.01, gamma = 0.005): split-BF16 rotating-frame steps followed by
+    the exact damping channels, against the same steps without them."""
+    import torch
+    w = ti.get("n11")
+    inst = w.instances[0]
+    m0 = pipeline.model_of(inst)
+    m1 = tcm.Model(m0.n, m0.c, m0.g, m0.omega_a, m0.omega_c, kappa=0.01, gamma=0.005)
+    _, U = pipeline.propagator(m0, w.dt)
+    out = {"workload": "tcm_n11_c5_N12288_open", "N": inst.N, "dtype": "bf16", "steps": steps,
+           "kappa": 0.01, "gamma": 0.005}
+    for key, m in (("unitary", m0), ("open", m1)):
+        rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
+        pipeline.evolve(m, U, rho.clone(), 2, w.dt, tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pop, _, _ = pipeline.evolve(m, U, rho, steps, w.dt, tcm.TC_GEMM_SPLIT_BF16,
+                                    tcm.TC_FRAME_ROTATING, w.renorm_every)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[key + "_ms_per_step"] = ms
+        out[key + "_final_excitation"] = float(pop[-1].item())
+    out["steps_per_s"] = 1000.0 / out["open_ms_per_step"]
+    out["dissipation_ms_per_step"] = out["open_ms_per_step"] - out["unitary_ms_per_step"]
+    del U
+    return out
+
+
 def cpu_baseline(U_np, rho_np, target_s=15.0):
     """The oracle's dense step (U rho U^dag with numpy products) on a row slab of
     the same N = 12288 matrices, timed on the host cores; scaled to steps/s.
@@ -238,7 +269,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="split,fp64,fp32")
-    ap.add_argument("--extras", default="n9,batch64,grad8",
+    ap.add_argument("--extras", default="n9,batch64,grad8,open11",
                     help="other workloads measured after the headline one ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
@@ -360,7 +391,8 @@ def main():
     if extras:
         out["other_workloads"] = {}
     for e in extras:
-        fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8}[e]
+        fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8,
+              "open11": bench_open11}[e]
         out["other_workloads"][e] = fn(tcm, pipeline, ti)
         log(f"{e}: {out['other_workloads'][e]}")
         torch.cuda.empty_cache()
