@@ -229,6 +229,115 @@ def bench_open11(tcm, pipeline, ti, steps=20):
     return out
 
 
+def bench_dense12(tcm, pipeline, ti, steps=20, steps64=2):
+    """Dense control at N = 12288: U from a dense random real symmetric H with
+    ||H dt|| ~ 0.8 and a dense random pure rho, against the TCM workload's own
+    U and rho0, both in the lab frame (the rotating frame is exact only for a
+    U that commutes with the excitation number), split-BF16 and FP64.  The
+    product kernels do the same work on any values; this shows what the exact
+    zeros of the TCM operands do to their time (clocks, power)."""
+    import torch
+    w = ti.get("n11")
+    inst = w.instances[0]
+    m = pipeline.model_of(inst)
+    N, dt = inst.N, w.dt
+    Hn, psi = ti.dense_control(N, dt)
+    H = torch.from_numpy(Hn).to("cuda")
+    del Hn
+    # Gershgorin interval of the control H (any valid bound sets the scaling)
+    off = H.abs().sum(dim=1) - H.diagonal().abs()
+    lo = float((H.diagonal() - off).min().item())
+    hi = float((H.diagonal() + off).max().item())
+    Ud = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    tcm.tc_expm(H, dt, lo, hi, Ud)
+    del H, off
+    psi_t = torch.from_numpy(psi).to("cuda")
+    rho_d = torch.outer(psi_t, psi_t.conj())
+    _, Ut = pipeline.propagator(m, dt)
+    rho_t = torch.from_numpy(inst.rho0()).to("cuda")
+    out = {"workload": "dense_control_N12288", "N": N, "norm_H_dt": 0.8, "steps": steps,
+           "steps_fp64": steps64, "frame": "lab"}
+    cases = (("dense", Ud, rho_d), ("tcm", Ut, rho_t))
+    for mode, key, dtype, K in ((tcm.TC_GEMM_SPLIT_BF16, "split", torch.complex64, steps),
+                                (tcm.TC_GEMM_F64, "fp64", torch.complex128, steps64)):
+        kind = {tcm.TC_GEMM_F64: tcm.TC_KERNEL_GEMM_F64,
+                tcm.TC_GEMM_SPLIT_BF16: tcm.TC_KERNEL_SPLIT_BF16}[mode]
+        for name, U, rho0 in cases:
+            r = rho0.to(dtype)
+            pipeline.evolve(m, U, r.clone(), 1, dt, mode, tcm.TC_FRAME_LAB, w.renorm_every)
+            torch.cuda.synchronize()
+            tcm.tc_profile_enable(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pipeline.evolve(m, U, r, K, dt, mode, tcm.TC_FRAME_LAB, w.renorm_every)
+            e1.record()
+            torch.cuda.synchronize()
+            kms, kl = tcm.tc_profile_read(kind)
+            tcm.tc_profile_enable(False)
+            out[f"{key}_{name}_ms_per_step"] = e0.elapsed_time(e1) / K
+            out[f"{key}_{name}_product_ms"] = kms / max(1, kl)
+            del r
+        out[f"{key}_dense_over_tcm"] = (out[f"{key}_dense_ms_per_step"]
+                                        / out[f"{key}_tcm_ms_per_step"])
+    del Ud, Ut, rho_d, rho_t
+    return out
+
+
+def sector_flop_per_step(n, c):
+    """Flops (8 per complex multiply-add) of one sector-block step: for every
+    excitation sector k (size d_k, first sorted position o_k) the first
+    product X_{k,k:} = U_k rho_{k,k:} is d_k x d_k x (N - o_k) and the second
+    rho'_{:k,k} = X_{:k,k} U_k^dag is (o_k + d_k) x d_k x d_k."""
+    from math import comb
+    d = [sum(comb(n, k - m) for m in range(min(k, c) + 1) if k - m <= n)
+         for k in range(n + c + 1)]
+    N = sum(d)
+    o = [sum(d[:k]) for k in range(len(d))]
+    return sum(8.0 * dk * dk * (N - ok) + 8.0 * dk * dk * (ok + dk) for dk, ok in zip(d, o))
+
+
+def bench_sectors11(tcm, pipeline, ti, steps=40):
+    """The N = 12288 workload stepped by excitation-sector blocks (opts.sectors):
+    FP64 (lab frame) and complex FP32 (rotating frame), renormalised every 20
+    steps.  Same result as the dense products (cross-sector entries of U are
+    exact zeros); 15.3x fewer flops per step."""
+    import torch
+    w = ti.get("n11")
+    inst = w.instances[0]
+    m = pipeline.model_of(inst)
+    N, dt = inst.N, w.dt
+    _, U = pipeline.propagator(m, dt)
+    fl = sector_flop_per_step(inst.n, inst.c)
+    out = {"workload": "tcm_n11_c5_N12288_sectors", "N": N, "steps": steps,
+           "flop_per_step": fl, "dense_flop_per_step": 16.0 * N ** 3}
+    for key, mode, frame, dtype, kind in (
+            ("fp64", tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, tcm.TC_KERNEL_GEMM_F64),
+            ("fp32", tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64,
+             tcm.TC_KERNEL_GEMM_F32)):
+        rho = torch.from_numpy(inst.rho0()).to("cuda").to(dtype)
+        pipeline.evolve(m, U, rho.clone(), 2, dt, mode, frame, w.renorm_every, sectors=True)
+        torch.cuda.synchronize()
+        tcm.tc_profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pipeline.evolve(m, U, rho, steps, dt, mode, frame, w.renorm_every, sectors=True)
+        e1.record()
+        torch.cuda.synchronize()
+        kms, kl = tcm.tc_profile_read(kind)
+        tcm.tc_profile_enable(False)
+        ms = e0.elapsed_time(e1) / steps
+        peak = PEAK_F64 if key == "fp64" else PEAK_F32
+        out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+                    "tflops": fl / (ms * 1e-3) / 1e12,
+                    "dense_equivalent_tflops": 16.0 * N ** 3 / (ms * 1e-3) / 1e12,
+                    "product_launches": kl, "product_ms": kms / max(1, kl),
+                    "product_frac_of_peak": (fl / 2.0) / (kms / max(1, kl) * 1e-3) / peak,
+                    "final_excitation": float(torch.real(torch.diagonal(rho)).sum().item())}
+        del rho
+    del U
+    return out
+
+
 def cpu_baseline(U_np, rho_np, target_s=15.0):
     """The oracle's dense step (U rho U^dag with numpy products) on a row slab of
     the same N = 12288 matrices, timed on the host cores; scaled to steps/s.
@@ -269,7 +378,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="split,fp64,fp32")
-    ap.add_argument("--extras", default="n9,batch64,grad8,open11",
+    ap.add_argument("--extras", default="n9,batch64,grad8,open11,dense12,sectors11",
                     help="other workloads measured after the headline one ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
@@ -392,7 +501,8 @@ def main():
         out["other_workloads"] = {}
     for e in extras:
         fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8,
-              "open11": bench_open11}[e]
+              "open11": bench_open11, "dense12": bench_dense12,
+              "sectors11": bench_sectors11}[e]
         out["other_workloads"][e] = fn(tcm, pipeline, ti)
         log(f"{e}: {out['other_workloads'][e]}")
         torch.cuda.empty_cache()

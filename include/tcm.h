@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TC_VERSION 100
+#define TC_VERSION 110
 
 /* Status codes. */
 #define TC_OK                     0
@@ -166,6 +166,23 @@ typedef struct {
   int32_t full_product;     /* 0: rho' = X U^dag is Hermitian, so its upper tile
                                triangle is multiplied and mirrored (rho(0) must be
                                Hermitian); 1: every tile of both products        */
+  int32_t sectors;          /* 0: dense N x N products.  1: excitation-sector
+                               block stepping (TC_GEMM_F64 / TC_GEMM_F32 only):
+                               H of Eq. (4) conserves k = m + |l|, so in the
+                               basis sorted by k (stable within a sector) U is
+                               block diagonal, U = diag(U_0 .. U_{n+c}), and
+                               rho'_{jk} = U_j rho_{jk} U_k^dag for every block
+                               pair.  Only the blocks j <= k are formed (rho is
+                               Hermitian; rho(0) must be), by two grouped
+                               products per step, X_{k,k:} = U_k rho_{k,k:} and
+                               rho'_{:k,k} = X_{:k,k} U_k^dag.  Same result as
+                               the dense products up to rounding (U's entries
+                               between sectors are exact zeros); the work per
+                               step is 8 sum_k d_k^2 (N + d_k) flop instead of
+                               16 N^3.  U is read at the call's start only;
+                               full_product is ignored; with a Lindblad term each
+                               step converts to the basis order and back around
+                               the damping channels.                            */
 } tc_evolve_opts;
 
 int tc_evolve_workspace_size(const tc_instance* inst, int32_t count,

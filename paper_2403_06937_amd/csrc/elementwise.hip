@@ -253,8 +253,11 @@ __global__ void damp_cavity_kernel(E* __restrict__ rho, int64_t ld, int n, int c
 }
 
 // ------------------------------------------------------- per-step readout
+// map == NULL: rho is in the basis order; else basis state s sits at row and
+// column map[s] of rho (the excitation-sorted order of the sector stepper).
 template <typename E>
 __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t ld,
+                               const int32_t* __restrict__ map,
                                double* __restrict__ pop, double* __restrict__ pdist) {
   __shared__ double sh[TPB];
   const int n = m.n;
@@ -264,7 +267,8 @@ __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t l
   for (int mm = 0; mm <= m.c; ++mm) {
     double part = 0.0, ex = 0.0;
     for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
-      const double d = double(rho[s * ld + s].re);
+      const int64_t q = map ? int64_t(map[s]) : s;
+      const double d = double(rho[q * ld + q].re);
       part += d;
       ex += double(popc64(uint64_t(s) & mask)) * d;
     }
@@ -730,15 +734,15 @@ int launch_dissipation_c64(const ModelArgs& m, c64* rho, int64_t ld, double dt, 
 }
 
 int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,
-                        double* pdist, hipStream_t s) {
-  hipLaunchKernelGGL(readout_kernel<c128>, dim3(1), dim3(TPB), 0, s, m, rho, ld, pop, pdist);
+                        double* pdist, hipStream_t s, const int32_t* map) {
+  hipLaunchKernelGGL(readout_kernel<c128>, dim3(1), dim3(TPB), 0, s, m, rho, ld, map, pop, pdist);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
 
 int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
-                       double* pdist, hipStream_t s) {
-  hipLaunchKernelGGL(readout_kernel<c64>, dim3(1), dim3(TPB), 0, s, m, rho, ld, pop, pdist);
+                       double* pdist, hipStream_t s, const int32_t* map) {
+  hipLaunchKernelGGL(readout_kernel<c64>, dim3(1), dim3(TPB), 0, s, m, rho, ld, map, pop, pdist);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }

@@ -30,6 +30,15 @@ struct InstPlan {
   void* X = nullptr; int64_t ldx = 0;
   double* scratch = nullptr;    // [4]: trace, non-finite flag, ...
   SplitPlanes planes;           // split-BF16 operand planes
+  // excitation-sector stepping (opts.sectors): rho and X in the sorted order
+  bool sectors = false;
+  std::vector<int64_t> soff, sdim;   // sector k: sorted positions [soff[k], soff[k] + sdim[k])
+  std::vector<size_t> boff;          // element offset of block k in blocks
+  int32_t* perm = nullptr;           // device [N]: basis state at sorted position
+  int32_t* inv = nullptr;            // device [N]: sorted position of basis state
+  void* blocks = nullptr;            // U_k (lab) or D_k = e^{i w_c k dt} U_k - I (rotating)
+  char* items = nullptr;             // descriptors of the two grouped products
+  GroupedProducts g1, g2;
 };
 
 int validate_opts(const tc_evolve_opts* o) {
@@ -43,6 +52,11 @@ int validate_opts(const tc_evolve_opts* o) {
   TC_CHECK_ARG(o->record_every >= 0, "record_every < 0");
   TC_CHECK_ARG(o->checkpoint_every >= 0, "checkpoint_every < 0");
   TC_CHECK_ARG(std::isfinite(o->dt), "dt not finite");
+  TC_CHECK_ARG(o->sectors == 0 || o->sectors == 1, "sectors must be 0 or 1");
+  if (o->sectors && o->gemm_mode == TC_GEMM_SPLIT_BF16) {
+    set_error("sector stepping runs TC_GEMM_F64 or TC_GEMM_F32 products");
+    return TC_ERR_UNSUPPORTED;
+  }
   return TC_OK;
 }
 
@@ -59,6 +73,42 @@ int validate_instance(const tc_instance* in, const tc_evolve_opts* o, ModelArgs*
   return TC_OK;
 }
 
+// Sector sizes d_k = sum_m binom(n, k - m) (m = 0..min(k, c)), k = 0..n + c.
+void sector_sizes(int n, int c, std::vector<int64_t>& dim, std::vector<int64_t>& off) {
+  std::vector<int64_t> binom(n + 1, 0);
+  binom[0] = 1;
+  for (int i = 1; i <= n; ++i)
+    for (int j = i; j >= 1; --j) binom[j] += binom[j - 1];
+  dim.assign(n + c + 1, 0);
+  off.assign(n + c + 1, 0);
+  for (int k = 0; k <= n + c; ++k) {
+    for (int mm = 0; mm <= std::min(k, c); ++mm)
+      if (k - mm <= n) dim[k] += binom[k - mm];
+    if (k > 0) off[k] = off[k - 1] + dim[k - 1];
+  }
+}
+
+void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
+  const int64_t N = p->N;
+  const size_t NN = size_t(N) * size_t(N);
+  const size_t eb = o.gemm_mode == TC_GEMM_F64 ? 16 : 8;
+  p->sectors = true;
+  sector_sizes(p->m.n, p->m.c, p->sdim, p->soff);
+  const int ns = int(p->sdim.size());
+  p->boff.assign(ns, 0);
+  size_t tot = 0;
+  for (int k = 0; k < ns; ++k) {
+    p->boff[k] = tot;
+    tot += size_t(p->sdim[k]) * size_t(p->sdim[k]);
+  }
+  p->rho = ar.take(NN * eb); p->ldr = N; p->rho_converted = true;
+  p->X = ar.take(NN * eb); p->ldx = N;
+  p->blocks = ar.take(tot * eb);
+  p->perm = static_cast<int32_t*>(ar.take(size_t(N) * 4));
+  p->inv = static_cast<int32_t*>(ar.take(size_t(N) * 4));
+  p->items = static_cast<char*>(ar.take(2 * grouped_bytes(ns)));
+}
+
 // Lays out (or sizes, when ar.base == nullptr) the workspace of one instance.
 void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelArgs& m, Arena& ar,
                    InstPlan* p) {
@@ -67,6 +117,10 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
   p->m = m;
   p->N = N;
   p->scratch = static_cast<double*>(ar.take(4 * sizeof(double)));
+  if (o.sectors) {
+    plan_sectors(o, ar, p);
+    return;
+  }
   if (o.gemm_mode == TC_GEMM_F64) {
     if (o.rho_dtype == TC_C128) {
       p->rho = in.rho; p->ldr = in.ldr; p->rho_converted = false;
@@ -95,14 +149,75 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
 int readout(const InstPlan& p, const tc_evolve_opts& o, double* pop, double* pdist,
             hipStream_t s) {
   if (o.gemm_mode == TC_GEMM_F64)
-    return launch_readout_c128(p.m, static_cast<const c128*>(p.rho), p.ldr, pop, pdist, s);
-  return launch_readout_c64(p.m, static_cast<const c64*>(p.rho), p.ldr, pop, pdist, s);
+    return launch_readout_c128(p.m, static_cast<const c128*>(p.rho), p.ldr, pop, pdist, s,
+                               p.inv);
+  return launch_readout_c64(p.m, static_cast<const c64*>(p.rho), p.ldr, pop, pdist, s, p.inv);
+}
+
+// Sector order: rebuilds the lower block triangle of rho hat from the upper one
+// (the stepper forms only blocks j <= k).
+int mirror(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (o.gemm_mode == TC_GEMM_F64)
+    return launch_mirror_lower_c128(static_cast<c128*>(p.rho), p.ldr, p.N, p.perm, p.m.n, s);
+  return launch_mirror_lower_c64(static_cast<c64*>(p.rho), p.ldr, p.N, p.perm, p.m.n, s);
+}
+
+// Sector order -> basis order: dst[s][t] = rho hat[inv[s]][inv[t]] (after mirror).
+int unpermute_to(InstPlan& p, const tc_evolve_opts& o, void* dst, int64_t ldd, int dst_dtype,
+                 hipStream_t s) {
+  const int64_t N = p.N;
+  if (o.gemm_mode == TC_GEMM_F64) {
+    const c128* r = static_cast<const c128*>(p.rho);
+    return dst_dtype == TC_C128
+        ? launch_gather_c128_c128(r, p.ldr, p.inv, 0, 0, N, N, 1.0, 0.0, false,
+                                  static_cast<c128*>(dst), ldd, s)
+        : launch_gather_c128_c64(r, p.ldr, p.inv, 0, 0, N, N, 1.0, 0.0, false,
+                                 static_cast<c64*>(dst), ldd, s);
+  }
+  const c64* r = static_cast<const c64*>(p.rho);
+  return dst_dtype == TC_C128
+      ? launch_gather_c64_c128(r, p.ldr, p.inv, 0, 0, N, N, 1.0, 0.0, false,
+                               static_cast<c128*>(dst), ldd, s)
+      : launch_gather_c64_c64(r, p.ldr, p.inv, 0, 0, N, N, 1.0, 0.0, false,
+                              static_cast<c64*>(dst), ldd, s);
+}
+
+// Basis order -> sector order: rho hat[i][j] = src[perm[i]][perm[j]].
+int permute_from(InstPlan& p, const tc_evolve_opts& o, const void* src, int64_t lds, int src_dtype,
+                 hipStream_t s) {
+  const int64_t N = p.N;
+  if (o.gemm_mode == TC_GEMM_F64) {
+    c128* r = static_cast<c128*>(p.rho);
+    return src_dtype == TC_C128
+        ? launch_gather_c128_c128(static_cast<const c128*>(src), lds, p.perm, 0, 0, N, N, 1.0,
+                                  0.0, false, r, p.ldr, s)
+        : launch_gather_c64_c128(static_cast<const c64*>(src), lds, p.perm, 0, 0, N, N, 1.0,
+                                 0.0, false, r, p.ldr, s);
+  }
+  c64* r = static_cast<c64*>(p.rho);
+  return src_dtype == TC_C128
+      ? launch_gather_c128_c64(static_cast<const c128*>(src), lds, p.perm, 0, 0, N, N, 1.0, 0.0,
+                               false, r, p.ldr, s)
+      : launch_gather_c64_c64(static_cast<const c64*>(src), lds, p.perm, 0, 0, N, N, 1.0, 0.0,
+                              false, r, p.ldr, s);
 }
 
 // exp(dt L) after a unitary step when the model has a Lindblad term; in the
 // split form the next step's rho^T planes are re-split from the damped master.
 int dissipate(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   if (!(p.m.kappa > 0.0 || p.m.gamma > 0.0)) return TC_OK;
+  if (p.sectors) {
+    // the damping channels act on the basis order: convert into X (free
+    // between steps), damp, convert back
+    const int md = o.gemm_mode == TC_GEMM_F64 ? TC_C128 : TC_C64;
+    TC_RETURN_IF(mirror(p, o, s));
+    TC_RETURN_IF(unpermute_to(p, o, p.X, p.ldx, md, s));
+    if (md == TC_C128)
+      TC_RETURN_IF(launch_dissipation_c128(p.m, static_cast<c128*>(p.X), p.ldx, o.dt, s));
+    else
+      TC_RETURN_IF(launch_dissipation_c64(p.m, static_cast<c64*>(p.X), p.ldx, o.dt, s));
+    return permute_from(p, o, p.X, p.ldx, md, s);
+  }
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_dissipation_c128(p.m, static_cast<c128*>(p.rho), p.ldr, o.dt, s);
   TC_RETURN_IF(launch_dissipation_c64(p.m, static_cast<c64*>(p.rho), p.ldr, o.dt, s));
@@ -112,6 +227,7 @@ int dissipate(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
 }
 
 int renorm(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (p.sectors) TC_RETURN_IF(mirror(p, o, s));
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_renorm_c128(static_cast<c128*>(p.rho), p.ldr, p.N, p.scratch, s);
   TC_RETURN_IF(launch_renorm_c64(static_cast<c64*>(p.rho), p.ldr, p.N, p.scratch, s));
@@ -146,7 +262,10 @@ int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_op
   const size_t NN = size_t(p.N) * size_t(p.N);
   char* dst = static_cast<char*>(in.checkpoints) + size_t(slot) * NN * eb;
   const bool master128 = o.gemm_mode == TC_GEMM_F64;
-  if (master128 && o.rho_dtype == TC_C128) {
+  if (p.sectors) {
+    TC_RETURN_IF(mirror(const_cast<InstPlan&>(p), o, s));
+    TC_RETURN_IF(unpermute_to(const_cast<InstPlan&>(p), o, dst, p.N, o.rho_dtype, s));
+  } else if (master128 && o.rho_dtype == TC_C128) {
     TC_TRY_HIP(hipMemcpy2DAsync(dst, p.N * 16, p.rho, p.ldr * 16, p.N * 16, p.N,
                                 hipMemcpyDeviceToDevice, s));
   } else if (!master128 && o.rho_dtype == TC_C64) {
@@ -168,7 +287,82 @@ int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_op
   return TC_OK;
 }
 
+// Sector stepping: sorted order, blocks of U (or D), and the descriptors of
+// the two grouped products of a step (largest sectors first, so the
+// persistent launch starts on the longest tiles).
+int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
+  const int64_t N = p.N;
+  const int n = p.m.n;
+  const int ns = int(p.sdim.size());
+  std::vector<int32_t> perm(N), inv(N);
+  std::vector<int64_t> next(p.soff);
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  for (int64_t st = 0; st < N; ++st) {
+    const int k = int(st >> n) + __builtin_popcountll(uint64_t(st) & mask);
+    const int64_t pos = next[k]++;
+    perm[pos] = int32_t(st);
+    inv[st] = int32_t(pos);
+  }
+  TC_TRY_HIP(hipMemcpyAsync(p.perm, perm.data(), size_t(N) * 4, hipMemcpyHostToDevice, s));
+  TC_TRY_HIP(hipMemcpyAsync(p.inv, inv.data(), size_t(N) * 4, hipMemcpyHostToDevice, s));
+  TC_TRY_HIP(hipStreamSynchronize(s));   // perm / inv are host memory of this call
+  TC_RETURN_IF(permute_from(p, o, in.rho, in.ldr, o.rho_dtype, s));
+  const bool rot = o.frame == TC_FRAME_ROTATING;
+  const bool f64 = o.gemm_mode == TC_GEMM_F64;
+  const size_t eb = f64 ? 16 : 8;
+  const c128* U = reinterpret_cast<const c128*>(in.U);
+  for (int k = 0; k < ns; ++k) {
+    // rotating frame: within sector k the frame factor e^{i w_c N dt} is the
+    // scalar e^{i w_c k dt}, so D_k = e^{i w_c k dt} U_k - I
+    double ph_re = 1.0, ph_im = 0.0;
+    if (rot) {
+      ph_re = std::cos(p.m.omega_c * double(k) * o.dt);
+      ph_im = std::sin(p.m.omega_c * double(k) * o.dt);
+    }
+    const int64_t off = p.soff[k], d = p.sdim[k];
+    char* blk = static_cast<char*>(p.blocks) + p.boff[k] * eb;
+    if (f64)
+      TC_RETURN_IF(launch_gather_c128_c128(U, in.ldu, p.perm, off, off, d, d, ph_re, ph_im, rot,
+                                           reinterpret_cast<c128*>(blk), d, s));
+    else
+      TC_RETURN_IF(launch_gather_c128_c64(U, in.ldu, p.perm, off, off, d, d, ph_re, ph_im, rot,
+                                          reinterpret_cast<c64*>(blk), d, s));
+  }
+  std::vector<int> order(ns);
+  for (int k = 0; k < ns; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return p.sdim[a] > p.sdim[b]; });
+  auto at = [&](void* base, int64_t r, int64_t c, int64_t ld) {
+    return static_cast<void*>(static_cast<char*>(base) + (size_t(r) * size_t(ld) + size_t(c)) * eb);
+  };
+  std::vector<GemmDesc> d1, d2;
+  for (int k : order) {
+    const int64_t off = p.soff[k], d = p.sdim[k];
+    const void* blk = static_cast<char*>(p.blocks) + p.boff[k] * eb;
+    GemmDesc g1;                        // X_{k, k:} = U_k rho_{k, k:}
+    g1.M = d; g1.N = N - off; g1.K = d;
+    g1.A = blk; g1.lda = d; g1.a_kmaj = false;
+    g1.B = at(p.rho, off, off, p.ldr); g1.ldb = p.ldr; g1.b_kmaj = true;
+    g1.C = at(p.X, off, off, p.ldx); g1.ldc = p.ldx;
+    if (rot) { g1.Cin = g1.B; g1.ldcin = p.ldr; g1.beta_re = 1.0; }
+    GemmDesc g2;                        // rho'_{:k, k} = X_{:k, k} U_k^dag
+    g2.M = off + d; g2.N = d; g2.K = d;
+    g2.A = at(p.X, 0, off, p.ldx); g2.lda = p.ldx; g2.a_kmaj = false;
+    g2.B = blk; g2.ldb = d; g2.b_kmaj = true; g2.conj_b = true;
+    g2.C = at(p.rho, 0, off, p.ldr); g2.ldc = p.ldr;
+    if (rot) { g2.Cin = g2.A; g2.ldcin = p.ldx; g2.beta_re = 1.0; }
+    d1.push_back(g1);
+    d2.push_back(g2);
+  }
+  const int v = tile_variant_for(N, f64);
+  TC_RETURN_IF(grouped_build(d1, f64, v, p.items, &p.g1, s));
+  TC_RETURN_IF(grouped_build(d2, f64, v, p.items + grouped_bytes(ns), &p.g2, s));
+  return TC_OK;
+}
+
 int prepare(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  if (p.sectors) return prepare_sectors(p, in, o, s);
   TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
   // master state
   if (p.rho_converted) {
@@ -199,6 +393,17 @@ int prepare(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStre
 
 int finish(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
   const double T = double(o.steps) * o.dt;
+  if (p.sectors) {
+    TC_RETURN_IF(mirror(p, o, s));
+    TC_RETURN_IF(unpermute_to(p, o, in.rho, in.ldr, o.rho_dtype, s));
+    if (o.frame == TC_FRAME_ROTATING && T != 0.0) {
+      if (o.rho_dtype == TC_C128)
+        TC_RETURN_IF(launch_frame_phase_c128(p.m, static_cast<c128*>(in.rho), in.ldr, T, s));
+      else
+        TC_RETURN_IF(launch_frame_phase_c64(p.m, static_cast<c64*>(in.rho), in.ldr, T, s));
+    }
+    return TC_OK;
+  }
   if (o.frame == TC_FRAME_ROTATING && T != 0.0) {
     if (o.gemm_mode == TC_GEMM_F64)
       TC_RETURN_IF(launch_frame_phase_c128(p.m, static_cast<c128*>(p.rho), p.ldr, T, s));
@@ -217,6 +422,10 @@ int finish(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStrea
 }
 
 int step(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (p.sectors) {
+    TC_RETURN_IF(grouped_run(p.g1, s));
+    return grouped_run(p.g2, s);
+  }
   if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
     return step_split(static_cast<c64*>(p.rho), p.ldr, static_cast<c64*>(p.X), p.ldx, p.N,
                       o.frame == TC_FRAME_ROTATING, o.full_product == 0, p.planes, s);
@@ -257,7 +466,7 @@ struct BatchBufs {
 };
 
 bool use_batched(int count, const tc_evolve_opts& o) {
-  return count > 1 && o.gemm_mode != TC_GEMM_SPLIT_BF16;
+  return count > 1 && o.gemm_mode != TC_GEMM_SPLIT_BF16 && !o.sectors;
 }
 
 void plan_batch(Arena& ar, int count, BatchBufs* b) {

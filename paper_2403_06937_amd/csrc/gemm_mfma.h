@@ -39,7 +39,8 @@ int gemm_f32(const GemmDesc& d, hipStream_t s);   // elements float / cplx<float
 
 // Grouped complex products (A and B row-major, the layout of the time step):
 // every product of the group shares one tile shape and one persistent launch.
-//   variant 1: 128 x 128 tiles, 8 waves;  variant 2: 64 x 64 tiles, 4 waves.
+//   variant 1: 128 x 128 tiles, 8 waves (K tile 16 for FP64, as the one-product
+//              FP64 default);  variant 2: 64 x 64 tiles, 4 waves.
 struct GroupedProducts {
   int variant = 1;
   bool f64 = false;

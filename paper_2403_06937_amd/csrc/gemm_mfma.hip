@@ -142,12 +142,55 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
   tn = in_group / gsize;
 }
 
+// Global-memory element access.  The persistent kernel reads its operand
+// pointers from the descriptor array rather than from kernel arguments, so
+// the compiler cannot infer their address space and would issue flat
+// accesses (which also count against lgkmcnt, so the LDS barrier would wait
+// for them).  Loads and stores through address-space-1 pointers of scalar or
+// vector type (a struct copy would drop the address space) are global.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  typedef __attribute__((address_space(1))) const T gT;
+  return *(gT*)p;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> gload(const cplx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  typedef __attribute__((address_space(1))) const v2 gv2;
+  const v2 v = *(gv2*)p;
+  return cplx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T x) {
+  typedef __attribute__((address_space(1))) T gT;
+  *(gT*)p = x;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(cplx<T>* p, cplx<T> x) {
+  typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  typedef __attribute__((address_space(1))) v2 gv2;
+  *(gv2*)p = v2{x.re, x.im};
+}
+
+// LDS of one tile: two buffers of the A and B K tiles (K-major rows padded by
+// PADB bytes).  Declared by the kernels, so a kernel that instantiates the
+// tile for both the checked and the exact case still holds one copy.
+template <typename T, bool CPLX, int BM, int BN, int BKT, int PADB>
+struct TileLds {
+  typedef typename elem<T, CPLX>::type E;
+  static constexpr int PADE = PADB / int(sizeof(E));
+  static constexpr int LDA_S = BM + PADE;
+  static constexpr int LDB_S = BN + PADE;
+  static constexpr int elems = 2 * BKT * (LDA_S + LDB_S);
+};
+
 // One BM x BN output tile (tm, tn) of the product described by p.  Shared by
 // the one-product kernel and the persistent grouped kernel; the caller must
 // separate two calls in one workgroup by a barrier (the LDS is reused).
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
           int BM, int BN, int BKT, int WM, int WN, int PADB>
-__device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool mirror) {
+__device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool mirror,
+                                          typename elem<T, CPLX>::type* lds) {
   typedef typename elem<T, CPLX>::type E;
   typedef typename acc_t<T>::type A4;
   constexpr int WGN = BN / (16 * WN);
@@ -164,8 +207,10 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
   static_assert(AK ? NT % BM == 0 : NT % BKT == 0, "A staging pattern");
   static_assert(BK ? NT % BN == 0 : NT % BKT == 0, "B staging pattern");
 
-  __shared__ E sA[2][BKT][LDA_S];
-  __shared__ E sB[2][BKT][LDB_S];
+  typedef E ARow[BKT][LDA_S];
+  typedef E BRow[BKT][LDB_S];
+  ARow* sA = reinterpret_cast<ARow*>(lds);
+  BRow* sB = reinterpret_cast<BRow*>(lds + 2 * BKT * LDA_S);
 
   // kernel arguments into registers once
   const int64_t M = p.M, N = p.N, K = p.K;
@@ -219,14 +264,14 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
       if (CHECKED && (m0 + ma + j * dma >= M || k0 + ka + j * dka >= K))
         ra[j] = elem<T, CPLX>::zero();
       else
-        ra[j] = elem<T, CPLX>::cj(qa[j * sja], cja);
+        ra[j] = elem<T, CPLX>::cj(gload(qa + j * sja), cja);
     }
 #pragma unroll
     for (int j = 0; j < B_PT; ++j) {
       if (CHECKED && (n0 + nb + j * dnb >= N || k0 + kb + j * dkb >= K))
         rb[j] = elem<T, CPLX>::zero();
       else
-        rb[j] = elem<T, CPLX>::cj(qb[j * sjb], cjb);
+        rb[j] = elem<T, CPLX>::cj(gload(qb + j * sjb), cjb);
     }
   };
   auto store_tiles = [&](int buf) {
@@ -304,20 +349,20 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
           out.re = ar * xr - ai * xi;
           out.im = ar * xi + ai * xr;
           if (use_beta) {
-            const E y = Cin[citr ? col * ldcin + row : row * ldcin + col];
+            const E y = gload(Cin + (citr ? col * ldcin + row : row * ldcin + col));
             out.re += br * y.re - bi * y.im;
             out.im += br * y.im + bi * y.re;
           }
           if (row == col) out.re += gam;
         } else {
           out = ar * acc_re[i][j][r];
-          if (use_beta) out += br * Cin[citr ? col * ldcin + row : row * ldcin + col];
+          if (use_beta) out += br * gload(Cin + (citr ? col * ldcin + row : row * ldcin + col));
           if (row == col) out += gam;
         }
-        Cg[caddr] = out;
+        gstore(Cg + caddr, out);
         if (mirror) {
           if constexpr (CPLX) out.im = -out.im;
-          Cg[ctr ? row * ldc + col : col * ldc + row] = out;
+          gstore(Cg + (ctr ? row * ldc + col : col * ldc + row), out);
         }
       }
 }
@@ -326,12 +371,15 @@ template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
           int BM, int BN, int BKT, int WM, int WN, int PADB>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
 gemm_kernel(const Params p) {
+  typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
+  __shared__ typename L::E lds[L::elems];
   int tm, tn;
   if (p.herm)
     tri_coords(xcd_linear(blockIdx.x, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
   else
     tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
-  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, p.herm && tm != tn);
+  gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, p.herm && tm != tn,
+                                                                 lds);
 }
 
 // Persistent grouped products: items[0 .. count) each describe one product
@@ -349,6 +397,8 @@ template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int 
           int PADB>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
 grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
+  typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
+  __shared__ typename L::E lds[L::elems];
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     int lo = 0, hi = count - 1;          // last item with tile_begin <= t
     while (lo < hi) {
@@ -366,9 +416,9 @@ grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
     }
     const bool mirror = p.herm && tm != tn;
     if (items[lo].exact)
-      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror);
+      gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror, lds);
     else
-      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror);
+      gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror, lds);
     __syncthreads();
   }
 }
@@ -557,7 +607,7 @@ int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* 
   typedef Variants<float, true> VF;
   int rc;
   if (f64)
-    rc = variant == 1 ? build_items<VD::V1>(ds, items, &total) : build_items<VD::V2>(ds, items, &total);
+    rc = variant == 1 ? build_items<VD::V6>(ds, items, &total) : build_items<VD::V2>(ds, items, &total);
   else
     rc = variant == 1 ? build_items<VF::V1>(ds, items, &total) : build_items<VF::V2>(ds, items, &total);
   TC_RETURN_IF(rc);
@@ -578,7 +628,7 @@ int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* 
 int grouped_run(const GroupedProducts& g, hipStream_t s) {
   if (g.count == 0 || g.total_tiles == 0) return TC_OK;
   if (g.f64)
-    return g.variant == 1 ? grouped_launch_t<double, Variants<double, true>::V1>(g, s)
+    return g.variant == 1 ? grouped_launch_t<double, Variants<double, true>::V6>(g, s)
                           : grouped_launch_t<double, Variants<double, true>::V2>(g, s);
   return g.variant == 1 ? grouped_launch_t<float, Variants<float, true>::V1>(g, s)
                         : grouped_launch_t<float, Variants<float, true>::V2>(g, s);

@@ -44,11 +44,12 @@ int launch_dissipation_c128(const ModelArgs& m, c128* rho, int64_t ld, double dt
 int launch_dissipation_c64(const ModelArgs& m, c64* rho, int64_t ld, double dt, hipStream_t s);
 
 // Per-step readout of the diagonal: pop[r] = sum_s |l(s)| Re rho_ss and, if
-// pdist != NULL, pdist[r*(c+1) + m] = sum_{photon(s) = m} Re rho_ss.
+// pdist != NULL, pdist[r*(c+1) + m] = sum_{photon(s) = m} Re rho_ss.  With a
+// map, basis state s is row and column map[s] of rho (sector-sorted order).
 int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,
-                        double* pdist, hipStream_t s);
+                        double* pdist, hipStream_t s, const int32_t* map = nullptr);
 int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
-                       double* pdist, hipStream_t s);
+                       double* pdist, hipStream_t s, const int32_t* map = nullptr);
 
 // Readout of many instances in one launch (one workgroup each): record index
 // r = *counter; pop[r] and pdist[r*(c+1) + m] as above.  advance_counter adds 1.
@@ -95,6 +96,29 @@ int launch_identity_c128(c128* X, int64_t ld, int64_t N, hipStream_t s);
 //   grad_delta[i] = 2 dt Im( ph sum_{s: l_i = 1} G_ss )
 int launch_grad_trace(const ModelArgs& m, const c128* G, int64_t ld, double ph_re, double ph_im,
                       double dt, double* grad_g, double* grad_delta, hipStream_t s);
+
+// ---- excitation-sector stepping (sectors.hip)
+// dst[i][j] = ph * src[map[ro + i]][map[co + j]] - sub_identity * [ro + i == co + j]
+// for i < rows, j < cols, with type conversion (ph = (ph_re, ph_im)).
+int launch_gather_c128_c128(const c128* src, int64_t lds, const int32_t* map, int64_t ro,
+                            int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,
+                            bool sub_identity, c128* dst, int64_t ldd, hipStream_t s);
+int launch_gather_c128_c64(const c128* src, int64_t lds, const int32_t* map, int64_t ro,
+                           int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,
+                           bool sub_identity, c64* dst, int64_t ldd, hipStream_t s);
+int launch_gather_c64_c64(const c64* src, int64_t lds, const int32_t* map, int64_t ro,
+                          int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,
+                          bool sub_identity, c64* dst, int64_t ldd, hipStream_t s);
+int launch_gather_c64_c128(const c64* src, int64_t lds, const int32_t* map, int64_t ro,
+                           int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,
+                           bool sub_identity, c128* dst, int64_t ldd, hipStream_t s);
+// In the sector-sorted order (sorted position i holds basis state perm[i],
+// whose excitation number is sector(i)): rho[i][j] = conj(rho[j][i]) wherever
+// sector(i) > sector(j), i.e. the lower block triangle is rebuilt from the upper.
+int launch_mirror_lower_c128(c128* rho, int64_t ld, int64_t N, const int32_t* perm, int n,
+                             hipStream_t s);
+int launch_mirror_lower_c64(c64* rho, int64_t ld, int64_t N, const int32_t* perm, int n,
+                            hipStream_t s);
 
 // bfloat16 hi/lo split of binary32 values.
 int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);

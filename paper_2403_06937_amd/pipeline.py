@@ -44,7 +44,7 @@ def propagator(model: Model, dt: float, method: int = TC_EXPM_SS_TAYLOR, device=
 def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: float,
            gemm_mode: int = TC_GEMM_F64, frame: int = TC_FRAME_LAB, renorm_every: int = 0,
            record_every: int = 1, checkpoint_every: int = 0, record_photons: bool = False,
-           ws=None, full_product: bool = False):
+           ws=None, full_product: bool = False, sectors: bool = False):
     """Steps rho (device, complex128 or complex64) in place; returns the records
     (pop [R], photon distribution [R, c+1] or None, checkpoints or None)."""
     rho_dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
@@ -58,7 +58,7 @@ def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: flo
                          device=rho.device)
     opts = make_opts(steps, dt, gemm_mode, rho_dtype, frame, renorm_every,
                      record_every if record_every else 0, checkpoint_every,
-                     full_product=int(full_product))
+                     full_product=int(full_product), sectors=int(sectors))
     inst = make_instance(model, U, rho, pop, pd, ck)
     tc_evolve([inst], opts, ws=ws, device=rho.device)
     return pop, pd, ck

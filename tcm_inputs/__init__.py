@@ -225,6 +225,20 @@ def random_matrix(shape, seed: int, dtype=np.complex128) -> np.ndarray:
     return rng.standard_normal(shape).astype(dtype)
 
 
+def dense_control(N: int, dt: float, norm: float = 0.8, seed: int = 0):
+    """Dense stand-in with no zero structure, for timing only: a real symmetric
+    Gaussian matrix H (off-diagonal variance sigma^2, diagonal 2 sigma^2) scaled
+    so that its spectral radius, about 2 sigma sqrt(N), times dt is `norm`, and
+    a normalised complex Gaussian state psi of length N.  Returns (H, psi)."""
+    rng = np.random.default_rng([SEED_ROOT, 9000 + seed])
+    sigma = norm / (2.0 * np.sqrt(N) * dt)
+    H = rng.standard_normal((N, N))
+    H += H.T
+    H *= sigma / np.sqrt(2.0)
+    psi = gaussian_state(N, rng)
+    return H, psi
+
+
 def random_density(N: int, seed: int, rank: int = 1) -> np.ndarray:
     """Seeded random density matrix (Hermitian, PSD, unit trace)."""
     rng = np.random.default_rng([SEED_ROOT, 7000 + seed])

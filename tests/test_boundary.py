@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_dim():
-    assert tcm.tc_version() == 100
+    assert tcm.tc_version() == 110
     assert tcm.tc_dim(3, 3) == 32
     assert tcm.tc_dim(11, 5) == 12288
     assert tcm.tc_dim(1, 0) == 2
@@ -160,3 +160,38 @@ def test_dissipation_rates_checked_before_device_work():
     rc = tcm.lib().tc_evolve_backward_workspace_size(ctypes.byref(ok.struct), ok.N,
                                                      ctypes.byref(opts), ctypes.byref(sz))
     assert rc == tcm.TC_ERR_UNSUPPORTED
+
+
+def test_sector_option_validation_and_workspace():
+    """opts.sectors: only 0 / 1; split-BF16 products are refused before any
+    device work; the workspace holds rho and X in the sorted order, the
+    compact U blocks (sum_k d_k^2 elements) and the two index maps."""
+    from math import comb
+    n, c = 5, 2
+    m = tcm.Model(n, c, [0.01] * n, [1.0] * n)
+    N = m.N
+
+    class Fake:
+        def __init__(self, p, ld):
+            self.p, self.ld = p, ld
+
+        def data_ptr(self):
+            return self.p
+
+        def stride(self, i):
+            return self.ld
+
+    inst = tcm.make_instance(m, Fake(0x1000, N), Fake(0x2000, N))
+    with pytest.raises(tcm.TcmError) as e:
+        tcm.tc_evolve_workspace_size([inst], tcm.make_opts(10, 0.1, sectors=2))
+    assert e.value.code == tcm.TC_ERR_INVALID_ARGUMENT
+    with pytest.raises(tcm.TcmError) as e:
+        tcm.tc_evolve_workspace_size([inst], tcm.make_opts(10, 0.1, tcm.TC_GEMM_SPLIT_BF16,
+                                                           tcm.TC_C64, sectors=1))
+    assert e.value.code == tcm.TC_ERR_UNSUPPORTED
+    ws = tcm.tc_evolve_workspace_size([inst], tcm.make_opts(10, 0.1, sectors=1))
+    d = [sum(comb(n, k - mm) for mm in range(min(k, c) + 1) if k - mm <= n)
+         for k in range(n + c + 1)]
+    assert sum(d) == N
+    need = 2 * N * N * 16 + sum(x * x for x in d) * 16 + 2 * N * 4
+    assert need <= ws <= need + 64 * 1024

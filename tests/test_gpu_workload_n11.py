@@ -105,3 +105,26 @@ def test_propagator_sampled_entries(setup):
     assert np.all(Ug[k[:, None] != k[cols][None, :]] == 0)
     print(f"N=12288 U sampled-column error {err:.3e}", flush=True)
     assert err < 1e-13
+
+
+@pytest.mark.parametrize("mode,dtype,frame,tol", [
+    (tcm.TC_GEMM_F64, torch.complex128, tcm.TC_FRAME_LAB, 1e-10),
+    (tcm.TC_GEMM_F32, torch.complex64, tcm.TC_FRAME_ROTATING, 1e-5)])
+def test_sector_blocks_full_run(setup, mode, dtype, frame, tol):
+    """All 200 steps by excitation-sector blocks (opts.sectors = 1, the
+    launch configuration bench.py times for this form): every entry of the
+    final rho and the population records against the oracle."""
+    w, inst, model, U, P, O = setup
+    rho = torch.from_numpy(inst.rho0()).to("cuda").to(dtype)
+    t0 = time.time()
+    pop, _, _ = pipeline.evolve(model, U, rho, w.steps, w.dt, mode, frame, w.renorm_every, 1,
+                                sectors=True)
+    torch.cuda.synchronize()
+    print(f"gpu sector blocks mode={mode} {w.steps} steps {time.time() - t0:.2f}s", flush=True)
+    err = max_entry_error(rho.cpu().numpy().astype(np.complex128), P.psi(inst.psi0, w.steps * w.dt))
+    popn = pop.cpu().numpy()
+    perr = max(abs(popn[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * w.dt)) ** 2)))
+               for s in range(0, w.steps + 1, 10))
+    print(f"N=12288 sector blocks mode={mode}: max-entry error {err:.3e}, population error "
+          f"{perr:.3e}", flush=True)
+    assert err <= tol and perr <= tol
