@@ -31,11 +31,16 @@ struct InstPlan {
   double* scratch = nullptr;    // [4]: trace, non-finite flag, ...
   SplitPlanes planes;           // split-BF16 operand planes
   // excitation-sector stepping (opts.sectors): rho and X in the sorted order
+  // Each sector's positions are padded to a multiple of the product tile
+  // (padding states hold exact zeros), so every block product is whole tiles.
   bool sectors = false;
-  std::vector<int64_t> soff, sdim;   // sector k: sorted positions [soff[k], soff[k] + sdim[k])
-  std::vector<size_t> boff;          // element offset of block k in blocks
-  int32_t* perm = nullptr;           // device [N]: basis state at sorted position
-  int32_t* inv = nullptr;            // device [N]: sorted position of basis state
+  int64_t Np = 0;                    // padded dimension of the sorted order
+  std::vector<int64_t> sdim;         // d_k: states of sector k
+  std::vector<int64_t> spo, spd;     // sector k: padded positions [spo[k], spo[k] + spd[k])
+  std::vector<size_t> boff;          // element offset of block k (spd[k]^2) in blocks
+  int32_t* perm = nullptr;           // device [Np]: basis state at a position, -1 = padding
+  int32_t* inv = nullptr;            // device [N]: position of basis state
+  int32_t* secpos = nullptr;         // device [Np]: sector of a position
   void* blocks = nullptr;            // U_k (lab) or D_k = e^{i w_c k dt} U_k - I (rotating)
   char* items = nullptr;             // descriptors of the two grouped products
   GroupedProducts g1, g2;
@@ -90,22 +95,34 @@ void sector_sizes(int n, int c, std::vector<int64_t>& dim, std::vector<int64_t>&
 
 void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
   const int64_t N = p->N;
-  const size_t NN = size_t(N) * size_t(N);
-  const size_t eb = o.gemm_mode == TC_GEMM_F64 ? 16 : 8;
+  const bool f64 = o.gemm_mode == TC_GEMM_F64;
+  const size_t eb = f64 ? 16 : 8;
+  // pad to the edge of the grouped product's tile (128 or 64)
+  const int64_t q = tile_variant_for(N, f64) == 1 ? 128 : 64;
   p->sectors = true;
-  sector_sizes(p->m.n, p->m.c, p->sdim, p->soff);
+  std::vector<int64_t> off;
+  sector_sizes(p->m.n, p->m.c, p->sdim, off);
   const int ns = int(p->sdim.size());
+  p->spo.assign(ns, 0);
+  p->spd.assign(ns, 0);
   p->boff.assign(ns, 0);
+  int64_t pos = 0;
   size_t tot = 0;
   for (int k = 0; k < ns; ++k) {
+    p->spo[k] = pos;
+    p->spd[k] = (p->sdim[k] + q - 1) / q * q;
+    pos += p->spd[k];
     p->boff[k] = tot;
-    tot += size_t(p->sdim[k]) * size_t(p->sdim[k]);
+    tot += size_t(p->spd[k]) * size_t(p->spd[k]);
   }
-  p->rho = ar.take(NN * eb); p->ldr = N; p->rho_converted = true;
-  p->X = ar.take(NN * eb); p->ldx = N;
+  p->Np = pos;
+  const size_t NN = size_t(pos) * size_t(pos);
+  p->rho = ar.take(NN * eb); p->ldr = pos; p->rho_converted = true;
+  p->X = ar.take(NN * eb); p->ldx = pos;
   p->blocks = ar.take(tot * eb);
-  p->perm = static_cast<int32_t*>(ar.take(size_t(N) * 4));
+  p->perm = static_cast<int32_t*>(ar.take(size_t(pos) * 4));
   p->inv = static_cast<int32_t*>(ar.take(size_t(N) * 4));
+  p->secpos = static_cast<int32_t*>(ar.take(size_t(pos) * 4));
   p->items = static_cast<char*>(ar.take(2 * grouped_bytes(ns)));
 }
 
@@ -158,8 +175,8 @@ int readout(const InstPlan& p, const tc_evolve_opts& o, double* pop, double* pdi
 // (the stepper forms only blocks j <= k).
 int mirror(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   if (o.gemm_mode == TC_GEMM_F64)
-    return launch_mirror_lower_c128(static_cast<c128*>(p.rho), p.ldr, p.N, p.perm, p.m.n, s);
-  return launch_mirror_lower_c64(static_cast<c64*>(p.rho), p.ldr, p.N, p.perm, p.m.n, s);
+    return launch_mirror_lower_c128(static_cast<c128*>(p.rho), p.ldr, p.Np, p.secpos, s);
+  return launch_mirror_lower_c64(static_cast<c64*>(p.rho), p.ldr, p.Np, p.secpos, s);
 }
 
 // Sector order -> basis order: dst[s][t] = rho hat[inv[s]][inv[t]] (after mirror).
@@ -182,23 +199,23 @@ int unpermute_to(InstPlan& p, const tc_evolve_opts& o, void* dst, int64_t ldd, i
                               static_cast<c64*>(dst), ldd, s);
 }
 
-// Basis order -> sector order: rho hat[i][j] = src[perm[i]][perm[j]].
+// Basis order -> sector order: rho hat[i][j] = src[perm[i]][perm[j]] (0 at padding).
 int permute_from(InstPlan& p, const tc_evolve_opts& o, const void* src, int64_t lds, int src_dtype,
                  hipStream_t s) {
-  const int64_t N = p.N;
+  const int64_t Np = p.Np;
   if (o.gemm_mode == TC_GEMM_F64) {
     c128* r = static_cast<c128*>(p.rho);
     return src_dtype == TC_C128
-        ? launch_gather_c128_c128(static_cast<const c128*>(src), lds, p.perm, 0, 0, N, N, 1.0,
+        ? launch_gather_c128_c128(static_cast<const c128*>(src), lds, p.perm, 0, 0, Np, Np, 1.0,
                                   0.0, false, r, p.ldr, s)
-        : launch_gather_c64_c128(static_cast<const c64*>(src), lds, p.perm, 0, 0, N, N, 1.0,
+        : launch_gather_c64_c128(static_cast<const c64*>(src), lds, p.perm, 0, 0, Np, Np, 1.0,
                                  0.0, false, r, p.ldr, s);
   }
   c64* r = static_cast<c64*>(p.rho);
   return src_dtype == TC_C128
-      ? launch_gather_c128_c64(static_cast<const c128*>(src), lds, p.perm, 0, 0, N, N, 1.0, 0.0,
-                               false, r, p.ldr, s)
-      : launch_gather_c64_c64(static_cast<const c64*>(src), lds, p.perm, 0, 0, N, N, 1.0, 0.0,
+      ? launch_gather_c128_c64(static_cast<const c128*>(src), lds, p.perm, 0, 0, Np, Np, 1.0,
+                               0.0, false, r, p.ldr, s)
+      : launch_gather_c64_c64(static_cast<const c64*>(src), lds, p.perm, 0, 0, Np, Np, 1.0, 0.0,
                               false, r, p.ldr, s);
 }
 
@@ -211,12 +228,12 @@ int dissipate(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
     // between steps), damp, convert back
     const int md = o.gemm_mode == TC_GEMM_F64 ? TC_C128 : TC_C64;
     TC_RETURN_IF(mirror(p, o, s));
-    TC_RETURN_IF(unpermute_to(p, o, p.X, p.ldx, md, s));
+    TC_RETURN_IF(unpermute_to(p, o, p.X, p.N, md, s));
     if (md == TC_C128)
-      TC_RETURN_IF(launch_dissipation_c128(p.m, static_cast<c128*>(p.X), p.ldx, o.dt, s));
+      TC_RETURN_IF(launch_dissipation_c128(p.m, static_cast<c128*>(p.X), p.N, o.dt, s));
     else
-      TC_RETURN_IF(launch_dissipation_c64(p.m, static_cast<c64*>(p.X), p.ldx, o.dt, s));
-    return permute_from(p, o, p.X, p.ldx, md, s);
+      TC_RETURN_IF(launch_dissipation_c64(p.m, static_cast<c64*>(p.X), p.N, o.dt, s));
+    return permute_from(p, o, p.X, p.N, md, s);
   }
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_dissipation_c128(p.m, static_cast<c128*>(p.rho), p.ldr, o.dt, s);
@@ -227,10 +244,11 @@ int dissipate(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
 }
 
 int renorm(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  const int64_t n = p.sectors ? p.Np : p.N;
   if (p.sectors) TC_RETURN_IF(mirror(p, o, s));
   if (o.gemm_mode == TC_GEMM_F64)
-    return launch_renorm_c128(static_cast<c128*>(p.rho), p.ldr, p.N, p.scratch, s);
-  TC_RETURN_IF(launch_renorm_c64(static_cast<c64*>(p.rho), p.ldr, p.N, p.scratch, s));
+    return launch_renorm_c128(static_cast<c128*>(p.rho), p.ldr, n, p.scratch, s);
+  TC_RETURN_IF(launch_renorm_c64(static_cast<c64*>(p.rho), p.ldr, n, p.scratch, s));
   if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
     TC_RETURN_IF(split_state(static_cast<const c64*>(p.rho), p.ldr, p.N, p.planes, s));
   return TC_OK;
@@ -292,11 +310,11 @@ int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_op
 // persistent launch starts on the longest tiles).
 int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
   TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
-  const int64_t N = p.N;
+  const int64_t N = p.N, Np = p.Np;
   const int n = p.m.n;
   const int ns = int(p.sdim.size());
-  std::vector<int32_t> perm(N), inv(N);
-  std::vector<int64_t> next(p.soff);
+  std::vector<int32_t> perm(Np, -1), inv(N), sec(Np);
+  std::vector<int64_t> next(p.spo);
   const uint64_t mask = (uint64_t(1) << n) - 1;
   for (int64_t st = 0; st < N; ++st) {
     const int k = int(st >> n) + __builtin_popcountll(uint64_t(st) & mask);
@@ -304,9 +322,12 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
     perm[pos] = int32_t(st);
     inv[st] = int32_t(pos);
   }
-  TC_TRY_HIP(hipMemcpyAsync(p.perm, perm.data(), size_t(N) * 4, hipMemcpyHostToDevice, s));
+  for (int k = 0; k < ns; ++k)
+    for (int64_t i = 0; i < p.spd[k]; ++i) sec[p.spo[k] + i] = k;
+  TC_TRY_HIP(hipMemcpyAsync(p.perm, perm.data(), size_t(Np) * 4, hipMemcpyHostToDevice, s));
   TC_TRY_HIP(hipMemcpyAsync(p.inv, inv.data(), size_t(N) * 4, hipMemcpyHostToDevice, s));
-  TC_TRY_HIP(hipStreamSynchronize(s));   // perm / inv are host memory of this call
+  TC_TRY_HIP(hipMemcpyAsync(p.secpos, sec.data(), size_t(Np) * 4, hipMemcpyHostToDevice, s));
+  TC_TRY_HIP(hipStreamSynchronize(s));   // the maps are host memory of this call
   TC_RETURN_IF(permute_from(p, o, in.rho, in.ldr, o.rho_dtype, s));
   const bool rot = o.frame == TC_FRAME_ROTATING;
   const bool f64 = o.gemm_mode == TC_GEMM_F64;
@@ -314,13 +335,13 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
   const c128* U = reinterpret_cast<const c128*>(in.U);
   for (int k = 0; k < ns; ++k) {
     // rotating frame: within sector k the frame factor e^{i w_c N dt} is the
-    // scalar e^{i w_c k dt}, so D_k = e^{i w_c k dt} U_k - I
+    // scalar e^{i w_c k dt}, so D_k = e^{i w_c k dt} U_k - I (0 at padding)
     double ph_re = 1.0, ph_im = 0.0;
     if (rot) {
       ph_re = std::cos(p.m.omega_c * double(k) * o.dt);
       ph_im = std::sin(p.m.omega_c * double(k) * o.dt);
     }
-    const int64_t off = p.soff[k], d = p.sdim[k];
+    const int64_t off = p.spo[k], d = p.spd[k];
     char* blk = static_cast<char*>(p.blocks) + p.boff[k] * eb;
     if (f64)
       TC_RETURN_IF(launch_gather_c128_c128(U, in.ldu, p.perm, off, off, d, d, ph_re, ph_im, rot,
@@ -332,16 +353,16 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
   std::vector<int> order(ns);
   for (int k = 0; k < ns; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return p.sdim[a] > p.sdim[b]; });
+                   [&](int a, int b) { return p.spd[a] > p.spd[b]; });
   auto at = [&](void* base, int64_t r, int64_t c, int64_t ld) {
     return static_cast<void*>(static_cast<char*>(base) + (size_t(r) * size_t(ld) + size_t(c)) * eb);
   };
   std::vector<GemmDesc> d1, d2;
   for (int k : order) {
-    const int64_t off = p.soff[k], d = p.sdim[k];
+    const int64_t off = p.spo[k], d = p.spd[k];
     const void* blk = static_cast<char*>(p.blocks) + p.boff[k] * eb;
     GemmDesc g1;                        // X_{k, k:} = U_k rho_{k, k:}
-    g1.M = d; g1.N = N - off; g1.K = d;
+    g1.M = d; g1.N = Np - off; g1.K = d;
     g1.A = blk; g1.lda = d; g1.a_kmaj = false;
     g1.B = at(p.rho, off, off, p.ldr); g1.ldb = p.ldr; g1.b_kmaj = true;
     g1.C = at(p.X, off, off, p.ldx); g1.ldc = p.ldx;
@@ -358,6 +379,7 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
   const int v = tile_variant_for(N, f64);
   TC_RETURN_IF(grouped_build(d1, f64, v, p.items, &p.g1, s));
   TC_RETURN_IF(grouped_build(d2, f64, v, p.items + grouped_bytes(ns), &p.g2, s));
+  p.g1.persistent = p.g2.persistent = false;     // whole tiles: one workgroup each
   return TC_OK;
 }
 

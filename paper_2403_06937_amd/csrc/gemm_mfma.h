@@ -46,13 +46,23 @@ struct GroupedProducts {
   bool f64 = false;
   int count = 0;
   int total_tiles = 0;
+  bool all_exact = false;      // every product a multiple of the tile (unchecked kernel)
+  bool persistent = true;      // false (all_exact only): one workgroup per tile
   void* items_dev = nullptr;   // device copy of the descriptors (grouped_bytes(count))
+  // host copy of each product's first tile, tile count and K (the launch
+  // splits the tile list over the XCDs by work)
+  std::vector<int64_t> begins, tiles, ks;
 };
 size_t grouped_bytes(int count);
 // Builds the descriptors of ds and uploads them to items_dev (synchronises s).
 int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* items_dev,
                   GroupedProducts* g, hipStream_t s);
 int grouped_run(const GroupedProducts& g, hipStream_t s);
+// Tile ranges [bound[x], bound[x + 1]) of the 8 XCDs for a persistent launch
+// of grid workgroups (K tile bkt).
+void xcd_split(const std::vector<int64_t>& begins, const std::vector<int64_t>& tiles,
+               const std::vector<int64_t>& ks, int64_t total_tiles, int grid, int bkt,
+               int bound[9]);
 
 // Tile variant for an N x N x N complex product, from the autotuner's table
 // (or its defaults when no tuning ran and no cache file is set).

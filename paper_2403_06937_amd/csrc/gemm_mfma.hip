@@ -24,6 +24,7 @@
 #include "profile.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 namespace tcm {
@@ -255,23 +256,36 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
   E ra[A_PT], rb[B_PT];
   const int64_t ktiles = (K + BKT - 1) / BKT;
 
+  // Ragged tiles (CHECKED): every lane loads from an address clamped into the
+  // operand and zeroes the value if its (row, k) lies outside, so the loads
+  // stay unconditional (no exec-mask branches around them).
+  const E* __restrict__ A0 = static_cast<const E*>(p.A);
+  const E* __restrict__ B0 = static_cast<const E*>(p.B);
   auto load_tiles = [&](int64_t kt) {
     const E* qa = pa + kt * ska;
     const E* qb = pb + kt * skb;
     const int64_t k0 = kt * BKT;
 #pragma unroll
     for (int j = 0; j < A_PT; ++j) {
-      if (CHECKED && (m0 + ma + j * dma >= M || k0 + ka + j * dka >= K))
-        ra[j] = elem<T, CPLX>::zero();
-      else
+      if constexpr (CHECKED) {
+        const int64_t m = m0 + ma + j * dma, k = k0 + ka + j * dka;
+        const int64_t mc = m < M ? m : M - 1, kc = k < K ? k : K - 1;
+        const E v = gload(A0 + (AK ? kc * lda + mc : mc * lda + kc));
+        ra[j] = (m < M && k < K) ? elem<T, CPLX>::cj(v, cja) : elem<T, CPLX>::zero();
+      } else {
         ra[j] = elem<T, CPLX>::cj(gload(qa + j * sja), cja);
+      }
     }
 #pragma unroll
     for (int j = 0; j < B_PT; ++j) {
-      if (CHECKED && (n0 + nb + j * dnb >= N || k0 + kb + j * dkb >= K))
-        rb[j] = elem<T, CPLX>::zero();
-      else
+      if constexpr (CHECKED) {
+        const int64_t nn = n0 + nb + j * dnb, k = k0 + kb + j * dkb;
+        const int64_t nc = nn < N ? nn : N - 1, kc = k < K ? k : K - 1;
+        const E v = gload(B0 + (BK ? kc * ldb + nc : nc * ldb + kc));
+        rb[j] = (nn < N && k < K) ? elem<T, CPLX>::cj(v, cjb) : elem<T, CPLX>::zero();
+      } else {
         rb[j] = elem<T, CPLX>::cj(gload(qb + j * sjb), cjb);
+      }
     }
   };
   auto store_tiles = [&](int buf) {
@@ -393,13 +407,26 @@ struct GroupItem {
   int exact;        // M, N multiples of the tile and K of the K tile
 };
 
+// Tile ranges per XCD: the workgroups with id % 8 == x (one XCD) walk the
+// tiles [bound[x], bound[x + 1]) of the concatenated list, so the tiles that
+// run together on an XCD are neighbours that share operand panels in its L2.
+// The host cuts the list where the estimated work (K tiles per tile) reaches
+// each XCD's share of the workgroups.
+struct XcdSplit { int bound[9]; };
+
+// ALL_EXACT: every product of the launch is a multiple of the tile in M, N
+// and of the K tile in K, so only the unchecked tile is instantiated (fewer
+// registers than a kernel that holds both).
 template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
-          int PADB>
+          int PADB, bool ALL_EXACT>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
-grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
+grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, XcdSplit xs) {
   typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
   __shared__ typename L::E lds[L::elems];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+  const int x = blockIdx.x % 8;
+  const int nx = (int(gridDim.x) - x + 7) / 8;      // workgroups of XCD x
+  const int end = xs.bound[x + 1];
+  for (int t = xs.bound[x] + int(blockIdx.x) / 8; t < end; t += nx) {
     int lo = 0, hi = count - 1;          // last item with tile_begin <= t
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -410,17 +437,47 @@ grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, int total) {
     int tm, tn;
     if (p.herm) {
       tri_coords(local, p.tiles_m, tm, tn);
-    } else {
-      tm = local / p.tiles_n;
-      tn = local % p.tiles_n;
+    } else {                              // GROUP_M tile rows at a time, column by column
+      const int per_group = GROUP_M * p.tiles_n;
+      const int first_m = (local / per_group) * GROUP_M;
+      const int gsize = min(p.tiles_m - first_m, GROUP_M);
+      const int in_group = local % per_group;
+      tm = first_m + in_group % gsize;
+      tn = in_group / gsize;
     }
     const bool mirror = p.herm && tm != tn;
-    if (items[lo].exact)
+    if (ALL_EXACT || items[lo].exact)
       gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror, lds);
     else
       gemm_tile<T, CPLX, AK, BK, true, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, mirror, lds);
     __syncthreads();
   }
+}
+
+// One workgroup per tile of the concatenated list (every product a multiple
+// of the tile): no loop state across tiles, so the register count is that of
+// the one-product kernel, and the hardware hands out tiles as CUs free up
+// (the list is ordered by decreasing K, longest tiles first).
+template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
+          int PADB>
+__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
+grouped_tile_kernel(const GroupItem* __restrict__ items, int count) {
+  typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
+  __shared__ typename L::E lds[L::elems];
+  const int t = blockIdx.x;
+  int lo = 0, hi = count - 1;            // last item with tile_begin <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+  }
+  const Params p = items[lo].p;
+  const int local = t - items[lo].tile_begin;
+  const int per_group = GROUP_M * p.tiles_n;
+  const int first_m = (local / per_group) * GROUP_M;
+  const int gsize = min(p.tiles_m - first_m, GROUP_M);
+  const int in_group = local % per_group;
+  gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(
+      p, first_m + in_group % gsize, in_group / gsize, false, lds);
 }
 
 // Tile shapes (BM, BN, BKT, WM, WN); the wave count is (BM/16WM)(BN/16WN).
@@ -575,9 +632,48 @@ int device_cus() {
   return cus;
 }
 
-template <typename T, typename S>
+}  // namespace
+
+// Cuts the concatenated tile list into 8 ranges whose work is proportional to
+// each XCD's workgroup count (workgroup w runs on XCD w % 8); a tile's work is
+// its K tiles plus one for its epilogue.
+void xcd_split(const std::vector<int64_t>& begins, const std::vector<int64_t>& tiles,
+               const std::vector<int64_t>& ks, int64_t total_tiles, int grid, int bkt,
+               int bound[9]) {
+  double total_work = 0.0;
+  for (size_t i = 0; i < tiles.size(); ++i)
+    total_work += double(tiles[i]) * double((ks[i] + bkt - 1) / bkt + 1);
+  bound[0] = 0;
+  size_t item = 0;
+  int64_t t = 0;                 // first tile not yet assigned
+  double done = 0.0;             // work of tiles [0, t)
+  int wg_before = 0;
+  for (int x = 0; x < 8; ++x) {
+    wg_before += (grid - x + 7) / 8;
+    const double target = total_work * double(wg_before) / double(grid);
+    while (item < tiles.size()) {
+      const int64_t last = begins[item] + tiles[item];
+      const double w = double((ks[item] + bkt - 1) / bkt + 1);
+      if (t >= last) { ++item; continue; }
+      const int64_t need = int64_t(std::ceil((target - done) / w - 1e-9));
+      if (need <= 0) break;
+      const int64_t take = std::min<int64_t>(need, last - t);
+      t += take;
+      done += double(take) * w;
+      if (t < last) break;
+    }
+    // the last XCD that has workgroups takes whatever rounding left over
+    bound[x + 1] = x >= std::min(grid, 8) - 1 ? int(total_tiles)
+                                              : int(std::min<int64_t>(t, total_tiles));
+  }
+}
+
+namespace {
+
+template <typename T, typename S, bool ALL_EXACT>
 int grouped_launch_t(const GroupedProducts& g, hipStream_t s) {
-  auto kern = grouped_gemm_kernel<T, true, false, true, S::BM, S::BN, S::BKT, S::WM, S::WN, S::PADB>;
+  auto kern = grouped_gemm_kernel<T, true, false, true, S::BM, S::BN, S::BKT, S::WM, S::WN,
+                                  S::PADB, ALL_EXACT>;
   static int per_cu = -1;
   if (per_cu < 0) {
     int nb = 0;
@@ -587,9 +683,11 @@ int grouped_launch_t(const GroupedProducts& g, hipStream_t s) {
   const int64_t resident = int64_t(device_cus()) * per_cu;
   const int grid = int(std::min<int64_t>(g.total_tiles, resident));
   if (grid <= 0) return TC_OK;
+  XcdSplit xs;
+  xcd_split(g.begins, g.tiles, g.ks, g.total_tiles, grid, S::BKT, xs.bound);
   ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
   hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(unsigned(S::NT)), 0, s,
-                     static_cast<const GroupItem*>(g.items_dev), g.count, g.total_tiles);
+                     static_cast<const GroupItem*>(g.items_dev), g.count, xs);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -616,6 +714,15 @@ int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* 
   g->count = int(items.size());
   g->total_tiles = total;
   g->items_dev = items_dev;
+  g->all_exact = true;
+  for (const GroupItem& it : items) g->all_exact = g->all_exact && it.exact;
+  g->begins.clear(); g->tiles.clear(); g->ks.clear();
+  for (size_t i = 0; i < items.size(); ++i) {
+    const int64_t next = i + 1 < items.size() ? items[i + 1].tile_begin : total;
+    g->begins.push_back(items[i].tile_begin);
+    g->tiles.push_back(next - items[i].tile_begin);
+    g->ks.push_back(items[i].p.K);
+  }
   if (!items.empty()) {
     // one synchronous upload per call; the descriptors are reused by every step
     TC_TRY_HIP(hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(GroupItem),
@@ -625,13 +732,30 @@ int grouped_build(const std::vector<GemmDesc>& ds, bool f64, int variant, void* 
   return TC_OK;
 }
 
+template <typename T, typename S>
+int grouped_launch_tiles(const GroupedProducts& g, hipStream_t s) {
+  auto kern = grouped_tile_kernel<T, true, false, true, S::BM, S::BN, S::BKT, S::WM, S::WN,
+                                  S::PADB>;
+  ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
+  hipLaunchKernelGGL(kern, dim3(unsigned(g.total_tiles)), dim3(unsigned(S::NT)), 0, s,
+                     static_cast<const GroupItem*>(g.items_dev), g.count);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+template <typename T, typename S>
+int grouped_launch_any(const GroupedProducts& g, hipStream_t s) {
+  if (g.all_exact && !g.persistent) return grouped_launch_tiles<T, S>(g, s);
+  return g.all_exact ? grouped_launch_t<T, S, true>(g, s) : grouped_launch_t<T, S, false>(g, s);
+}
+
 int grouped_run(const GroupedProducts& g, hipStream_t s) {
   if (g.count == 0 || g.total_tiles == 0) return TC_OK;
   if (g.f64)
-    return g.variant == 1 ? grouped_launch_t<double, Variants<double, true>::V6>(g, s)
-                          : grouped_launch_t<double, Variants<double, true>::V2>(g, s);
-  return g.variant == 1 ? grouped_launch_t<float, Variants<float, true>::V1>(g, s)
-                        : grouped_launch_t<float, Variants<float, true>::V2>(g, s);
+    return g.variant == 1 ? grouped_launch_any<double, Variants<double, true>::V6>(g, s)
+                          : grouped_launch_any<double, Variants<double, true>::V2>(g, s);
+  return g.variant == 1 ? grouped_launch_any<float, Variants<float, true>::V1>(g, s)
+                        : grouped_launch_any<float, Variants<float, true>::V2>(g, s);
 }
 
 int gemm_f64(const GemmDesc& d, hipStream_t s) {

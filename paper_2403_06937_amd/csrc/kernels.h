@@ -99,7 +99,8 @@ int launch_grad_trace(const ModelArgs& m, const c128* G, int64_t ld, double ph_r
 
 // ---- excitation-sector stepping (sectors.hip)
 // dst[i][j] = ph * src[map[ro + i]][map[co + j]] - sub_identity * [ro + i == co + j]
-// for i < rows, j < cols, with type conversion (ph = (ph_re, ph_im)).
+// for i < rows, j < cols, with type conversion (ph = (ph_re, ph_im)); 0 where
+// either map entry is negative (a padding position).
 int launch_gather_c128_c128(const c128* src, int64_t lds, const int32_t* map, int64_t ro,
                             int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,
                             bool sub_identity, c128* dst, int64_t ldd, hipStream_t s);
@@ -112,13 +113,12 @@ int launch_gather_c64_c64(const c64* src, int64_t lds, const int32_t* map, int64
 int launch_gather_c64_c128(const c64* src, int64_t lds, const int32_t* map, int64_t ro,
                            int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,
                            bool sub_identity, c128* dst, int64_t ldd, hipStream_t s);
-// In the sector-sorted order (sorted position i holds basis state perm[i],
-// whose excitation number is sector(i)): rho[i][j] = conj(rho[j][i]) wherever
-// sector(i) > sector(j), i.e. the lower block triangle is rebuilt from the upper.
-int launch_mirror_lower_c128(c128* rho, int64_t ld, int64_t N, const int32_t* perm, int n,
+// In the sector-sorted order (position i in sector sec[i], sec non-decreasing):
+// rho[i][j] = conj(rho[j][i]) wherever sec[i] > sec[j], i.e. the lower block
+// triangle is rebuilt from the upper one.
+int launch_mirror_lower_c128(c128* rho, int64_t ld, int64_t N, const int32_t* sec,
                              hipStream_t s);
-int launch_mirror_lower_c64(c64* rho, int64_t ld, int64_t N, const int32_t* perm, int n,
-                            hipStream_t s);
+int launch_mirror_lower_c64(c64* rho, int64_t ld, int64_t N, const int32_t* sec, hipStream_t s);
 
 // bfloat16 hi/lo split of binary32 values.
 int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);

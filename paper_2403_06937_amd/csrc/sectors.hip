@@ -4,8 +4,10 @@
 // number k = m + |l| is conserved and, in the basis sorted by k (stable within
 // a sector), H and U = exp(-i H dt) are block diagonal.  The stepper keeps rho
 // in that sorted order ("rho hat"), multiplies the blocks, and converts at the
-// boundary with the gathers below.  Sorted position i holds basis state
-// perm[i]; basis state s sits at position inv[s].
+// boundary with the gathers below.  Each sector's positions are padded to a
+// multiple of the product tile with padding states that stay exactly zero.
+// Position i holds basis state perm[i] (-1 for padding) of sector sec[i];
+// basis state s sits at position inv[s].
 #include "kernels.h"
 
 namespace tcm {
@@ -14,15 +16,12 @@ namespace {
 constexpr int TPB = 256;
 constexpr int RT = 32;   // tile edge of the mirror kernel
 
-__device__ __forceinline__ int exc_of(int64_t s, int n) {
-  return int(s >> n) + __popcll(uint64_t(s) & ((uint64_t(1) << n) - 1));
-}
-
 template <typename E> struct real_of;
 template <> struct real_of<c128> { typedef double type; };
 template <> struct real_of<c64> { typedef float type; };
 
-// dst[i][j] = ph * src[map[ro + i]][map[co + j]] - sub * [ro + i == co + j]
+// dst[i][j] = ph * src[map[ro + i]][map[co + j]] - sub * [ro + i == co + j];
+// a negative map entry (a padding position) gives exactly 0.
 template <typename Ein, typename Eout>
 __global__ void gather_kernel(const Ein* __restrict__ src, int64_t lds,
                               const int32_t* __restrict__ map, int64_t ro, int64_t co,
@@ -34,10 +33,13 @@ __global__ void gather_kernel(const Ein* __restrict__ src, int64_t lds,
   const int64_t sc = map[co + j];
   for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
     const int64_t sr = map[ro + i];
-    const Ein v = src[sr * lds + sc];
-    double re = ph_re * double(v.re) - ph_im * double(v.im);
-    const double im = ph_re * double(v.im) + ph_im * double(v.re);
-    if (sub && ro + i == co + j) re -= 1.0;
+    double re = 0.0, im = 0.0;
+    if (sr >= 0 && sc >= 0) {
+      const Ein v = src[sr * lds + sc];
+      re = ph_re * double(v.re) - ph_im * double(v.im);
+      im = ph_re * double(v.im) + ph_im * double(v.re);
+      if (sub && ro + i == co + j) re -= 1.0;
+    }
     dst[i * ldd + j] = Eout{T(re), T(im)};
   }
 }
@@ -58,7 +60,7 @@ __device__ __forceinline__ void pair_of(int64_t b, int64_t& bi, int64_t& bj) {
 // before any write, so the pass is race-free in place.
 template <typename E>
 __global__ void mirror_lower_kernel(E* __restrict__ rho, int64_t ld, int64_t N,
-                                    const int32_t* __restrict__ perm, int n) {
+                                    const int32_t* __restrict__ sec) {
   typedef typename real_of<E>::type T;
   __shared__ E tS[RT][RT + 1];
   int64_t bi, bj;
@@ -66,7 +68,7 @@ __global__ void mirror_lower_kernel(E* __restrict__ rho, int64_t ld, int64_t N,
   const int64_t r0 = bj * RT, c0 = bi * RT;            // destination tile origin
   const int64_t rlast = min(r0 + RT, N) - 1;
   // nothing to write when the last row's sector does not exceed the first column's
-  if (exc_of(perm[rlast], n) <= exc_of(perm[c0], n)) return;
+  if (sec[rlast] <= sec[c0]) return;
   const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
   for (int r = ty; r < RT; r += TPB / RT) {
     const int64_t i = bi * RT + r, j = bj * RT + tx;
@@ -75,7 +77,7 @@ __global__ void mirror_lower_kernel(E* __restrict__ rho, int64_t ld, int64_t N,
   __syncthreads();
   for (int r = ty; r < RT; r += TPB / RT) {
     const int64_t i = r0 + r, j = c0 + tx;
-    if (i < N && j < N && exc_of(perm[i], n) > exc_of(perm[j], n)) {
+    if (i < N && j < N && sec[i] > sec[j]) {
       const E v = tS[tx][r];
       rho[i * ld + j] = E{v.re, T(-v.im)};
     }
@@ -95,12 +97,12 @@ int gather_impl(const Ein* src, int64_t lds, const int32_t* map, int64_t ro, int
 }
 
 template <typename E>
-int mirror_impl(E* rho, int64_t ld, int64_t N, const int32_t* perm, int n, hipStream_t s) {
+int mirror_impl(E* rho, int64_t ld, int64_t N, const int32_t* sec, hipStream_t s) {
   if (N <= 1) return TC_OK;
   const int64_t T = (N + RT - 1) / RT;
   const int64_t np = T * (T + 1) / 2;
   hipLaunchKernelGGL(mirror_lower_kernel<E>, dim3(unsigned(np)), dim3(TPB), 0, s, rho, ld, N,
-                     perm, n);
+                     sec);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -128,13 +130,12 @@ int launch_gather_c64_c128(const c64* src, int64_t lds, const int32_t* map, int6
   return gather_impl(src, lds, map, ro, co, rows, cols, ph_re, ph_im, sub_identity, dst, ldd, s);
 }
 
-int launch_mirror_lower_c128(c128* rho, int64_t ld, int64_t N, const int32_t* perm, int n,
+int launch_mirror_lower_c128(c128* rho, int64_t ld, int64_t N, const int32_t* sec,
                              hipStream_t s) {
-  return mirror_impl(rho, ld, N, perm, n, s);
+  return mirror_impl(rho, ld, N, sec, s);
 }
-int launch_mirror_lower_c64(c64* rho, int64_t ld, int64_t N, const int32_t* perm, int n,
-                            hipStream_t s) {
-  return mirror_impl(rho, ld, N, perm, n, s);
+int launch_mirror_lower_c64(c64* rho, int64_t ld, int64_t N, const int32_t* sec, hipStream_t s) {
+  return mirror_impl(rho, ld, N, sec, s);
 }
 
 }  // namespace tcm

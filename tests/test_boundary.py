@@ -164,8 +164,8 @@ def test_dissipation_rates_checked_before_device_work():
 
 def test_sector_option_validation_and_workspace():
     """opts.sectors: only 0 / 1; split-BF16 products are refused before any
-    device work; the workspace holds rho and X in the sorted order, the
-    compact U blocks (sum_k d_k^2 elements) and the two index maps."""
+    device work; the workspace holds rho and X in the padded sorted order,
+    the padded U blocks (sum_k D_k^2 elements) and the three index maps."""
     from math import comb
     n, c = 5, 2
     m = tcm.Model(n, c, [0.01] * n, [1.0] * n)
@@ -193,5 +193,9 @@ def test_sector_option_validation_and_workspace():
     d = [sum(comb(n, k - mm) for mm in range(min(k, c) + 1) if k - mm <= n)
          for k in range(n + c + 1)]
     assert sum(d) == N
-    need = 2 * N * N * 16 + sum(x * x for x in d) * 16 + 2 * N * 4
+    # each sector padded to a multiple of the product tile edge (64 at this N)
+    q = 128 if tcm.tc_autotune_query(tcm.TC_GEMM_F64, N) == 1 else 64
+    D = [-(-x // q) * q for x in d]
+    Np = sum(D)
+    need = 2 * Np * Np * 16 + sum(x * x for x in D) * 16 + 2 * Np * 4 + N * 4
     assert need <= ws <= need + 64 * 1024
