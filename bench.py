@@ -354,6 +354,63 @@ def bench_sectors11(tcm, pipeline, ti, steps=40):
     return out
 
 
+def bench_paper_sweep(tcm, pipeline, ti, ns=range(8, 16)):
+    """The paper's own model (the 2^n states of all-excited atoms, Sec. II and
+    IV) at N = 2^8 .. 2^15 on one GPU: the time to form L by Eq. (10)'s
+    ten-term series (the counterpart of Table I) and the time per step
+    rho <- L rho L^dag (of Table II, whose totals are over unstated step
+    counts), in FP64 and in split-BF16 (rotating frame)."""
+    import torch
+    rows = []
+    for n in ns:
+        w = ti.workload_paper(n)
+        inst = w.instances[0]
+        m = pipeline.model_of(inst)
+        k, dt, D = n, w.dt, 1 << n
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = pipeline.sector_hamiltonian(m, k)
+        torch.cuda.synchronize()
+        t_h = time.perf_counter() - t0
+        L = torch.empty((D, D), dtype=torch.complex128, device="cuda")
+        ws = torch.empty(tcm.tc_expm_workspace_size(D, tcm.TC_EXPM_TAYLOR10),
+                         dtype=torch.uint8, device="cuda")
+        tcm.tc_expm(H, dt, 0.0, 0.0, L, tcm.TC_EXPM_TAYLOR10, ws=ws)     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tcm.tc_expm(H, dt, 0.0, 0.0, L, tcm.TC_EXPM_TAYLOR10, ws=ws)
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - t0
+        del ws, H
+        row = {"n": n, "N": D, "hamiltonian_ms": 1e3 * t_h, "taylor10_ms": 1e3 * t_l}
+        for key, mode, frame, dtype in (
+                ("fp64", tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128),
+                ("split", tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64)):
+            steps = max(1, min(20, int(3e14 / (12.0 * D ** 3) if key == "fp64"
+                                       else 3e15 / (36.0 * D ** 3))))
+            rho = torch.zeros((D, D), dtype=dtype, device="cuda")
+            rho[0, 0] = 1.0                  # all excited: first state of the sector
+            pipeline.evolve_sector(m, k, L, rho.clone(), 1, dt, mode, frame)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pop, _, _ = pipeline.evolve_sector(m, k, L, rho, steps, dt, mode, frame)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            row[key + "_ms_per_step"] = ms
+            row[key + "_steps"] = steps
+            row[key + "_tflops"] = 16.0 * D ** 3 / (ms * 1e-3) / 1e12
+            row[key + "_final_excitation"] = float(pop[-1].item())
+            del rho
+        del L
+        torch.cuda.empty_cache()
+        rows.append(row)
+        log(f"paper model n={n}: {row}")
+    return {"workload": "tcm_paper_2n_sweep", "method": "Taylor-10 L (Eq. (10)), R = L^dag",
+            "rows": rows}
+
+
 def cpu_baseline(U_np, rho_np, target_s=15.0):
     """The oracle's dense step (U rho U^dag with numpy products) on a row slab of
     the same N = 12288 matrices, timed on the host cores; scaled to steps/s.
@@ -394,7 +451,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="split,fp64,fp32")
-    ap.add_argument("--extras", default="n9,batch64,grad8,open11,dense12,sectors11",
+    ap.add_argument("--extras", default="n9,batch64,grad8,open11,dense12,sectors11,paper",
                     help="other workloads measured after the headline one ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
@@ -518,7 +575,7 @@ def main():
     for e in extras:
         fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8,
               "open11": bench_open11, "dense12": bench_dense12,
-              "sectors11": bench_sectors11}[e]
+              "sectors11": bench_sectors11, "paper": bench_paper_sweep}[e]
         out["other_workloads"][e] = fn(tcm, pipeline, ti)
         log(f"{e}: {out['other_workloads'][e]}")
         torch.cuda.empty_cache()

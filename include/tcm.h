@@ -110,6 +110,27 @@ int tc_dim(int32_t n_atoms, int32_t photon_cutoff, int64_t* N);
  * leave |m, l> (O(N n) work). */
 int tc_spectral_bounds(const tc_model* m, double* lam_lo, double* lam_hi);
 
+/* ------------------------------------------- one excitation sector */
+
+/* H of Eq. (4) conserves the excitation number k = m + |l| (photons plus
+ * excited atoms), so it is block diagonal over the sectors k = 0 .. n + c, and
+ * so is U = exp(-i H dt).  These calls work on one block.  With c >= n and
+ * k = n the block is the paper's own model of Sec. II, Eq. (2): the 2^n atom
+ * patterns |l>, each with n - |l| photons, starting from all atoms excited
+ * (Sec. IV); the sector's states are ordered by increasing basis index.
+ * All are host-only except the builder, and fail with
+ * TC_ERR_INVALID_ARGUMENT unless 0 <= k <= n + c. */
+/* d_k = sum_m binom(n, k - m) over m = max(0, k - n) .. min(k, c). */
+int tc_sector_dim(const tc_model* m, int32_t k, int64_t* d);
+/* The basis indices s of sector k, increasing (states: host [d_k]). */
+int tc_sector_states(const tc_model* m, int32_t k, int64_t* states);
+/* Gershgorin interval of the block (a sector state couples only inside it). */
+int tc_sector_spectral_bounds(const tc_model* m, int32_t k, double* lam_lo, double* lam_hi);
+/* Writes the block H_k[i][j] = H[s_i][s_j] (device, d_k x d_k, ldh >= d_k,
+ * row-major, real symmetric) for the states s_0 < s_1 < ... of sector k. */
+int tc_build_sector_hamiltonian(const tc_model* m, int32_t k, double* H, int64_t ldh,
+                                void* stream);
+
 /* ----------------------------------------------------- a1: Hamiltonian */
 
 /* Writes the dense real symmetric Eq. (4) into H (device, N x N, row-major,
@@ -197,6 +218,21 @@ int tc_evolve_workspace_size(const tc_instance* inst, int32_t count,
  * when a renormalisation finds a non-finite trace (then TC_ERR_NONFINITE). */
 int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o,
               void* ws, size_t ws_bytes, void* stream);
+
+/* tc_evolve within excitation sector k: inst->N = d_k, inst->U the d_k x d_k
+ * propagator of the block (tc_expm of tc_build_sector_hamiltonian's H_k),
+ * inst->rho the d_k x d_k density matrix on the sector's states in the order
+ * of tc_sector_states.  Every step is Eq. (6) on the block; records use the
+ * basis states of the block (P(m) for m outside the sector is 0);
+ * checkpoints are d_k x d_k.  The rotating frame's factor is the scalar
+ * e^{i w_c k dt} here, so its operand is D = e^{i w_c k dt} U_k - I and the
+ * result needs no phase.  opts.sectors must be 0; a model with a Lindblad term
+ * gives TC_ERR_UNSUPPORTED (its damping channels lead out of the sector).
+ * One instance per call. */
+int tc_evolve_sector_workspace_size(const tc_instance* inst, int32_t k,
+                                    const tc_evolve_opts* o, size_t* bytes);
+int tc_evolve_sector(const tc_instance* inst, int32_t k, const tc_evolve_opts* o,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------ a5/a7: observables */
 

@@ -108,3 +108,27 @@ def sectors(n: int, c: int):
     diagonal in k because N_exc commutes with Eq. (4))."""
     kdiag = np.rint(total_excitation_diag(n, c)).astype(np.int64)
     return {int(k): np.nonzero(kdiag == k)[0] for k in np.unique(kdiag)}
+
+
+def paper_model_hamiltonian(n: int, g, omega_a, omega_c: float = 1.0) -> np.ndarray:
+    """The paper's atom-only model (Sec. II, Eq. (2) with the Hamiltonian of
+    Eq. (4)): the 2^n atom patterns l (atom i on bit n - 1 - i, 1 = excited),
+    each carrying the n - |l| photons that the all-excited start (Sec. IV)
+    leaves.  Written out element by element on those 2^n states, ordered by
+    the integer value of l:
+      H[l][l]   = w_c (n - |l|) + sum_i w_a,i l_i
+      H[l'][l]  = H[l][l'] = g_i sqrt(n - |l| + 1)  for l_i = 1, l' = l - e_i
+    (a^dag s_i^- takes |m, l> to sqrt(m + 1) |m + 1, l - e_i>, m = n - |l|)."""
+    g = np.asarray(g, dtype=np.float64)
+    omega_a = np.asarray(omega_a, dtype=np.float64)
+    D = 1 << n
+    H = np.zeros((D, D))
+    for l in range(D):
+        bits = [(l >> (n - 1 - i)) & 1 for i in range(n)]
+        m = n - sum(bits)
+        H[l, l] = omega_c * m + sum(omega_a[i] for i in range(n) if bits[i])
+        for i in range(n):
+            if bits[i]:
+                lp = l ^ (1 << (n - 1 - i))
+                H[lp, l] = H[l, lp] = g[i] * np.sqrt(m + 1)
+    return H

@@ -46,7 +46,8 @@ EXPORTED = [
     "tc_observables_workspace_size", "tc_observables", "tc_evolve_backward_workspace_size",
     "tc_evolve_backward", "tc_gemm_workspace_size", "tc_zgemm", "tc_split_bf16",
     "tc_profile_enable", "tc_profile_read", "tc_autotune_workspace_size", "tc_autotune",
-    "tc_autotune_query",
+    "tc_autotune_query", "tc_sector_dim", "tc_sector_states", "tc_sector_spectral_bounds",
+    "tc_build_sector_hamiltonian", "tc_evolve_sector_workspace_size", "tc_evolve_sector",
 ]
 
 TC_KERNEL_GEMM_F64 = 0
@@ -130,6 +131,12 @@ def lib():
             "tc_autotune_workspace_size": [i32, i64, P(sz)],
             "tc_autotune": [i32, i64, vp, sz, vp],
             "tc_autotune_query": [i32, i64, P(i32)],
+            "tc_sector_dim": [P(tc_model), i32, P(i64)],
+            "tc_sector_states": [P(tc_model), i32, vp],
+            "tc_sector_spectral_bounds": [P(tc_model), i32, P(f64), P(f64)],
+            "tc_build_sector_hamiltonian": [P(tc_model), i32, vp, i64, vp],
+            "tc_evolve_sector_workspace_size": [P(tc_instance), i32, P(tc_evolve_opts), P(sz)],
+            "tc_evolve_sector": [P(tc_instance), i32, P(tc_evolve_opts), vp, sz, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -261,6 +268,53 @@ def tc_evolve(instances, opts, ws=None, device=None, stream=None):
         ws = _workspace(need, device if device is not None else "cuda")
     _check(lib().tc_evolve(arr, len(instances), ctypes.byref(opts), _ptr(ws), ws.numel(),
                            _stream(stream)), "tc_evolve")
+
+
+def tc_sector_dim(model: Model, k: int) -> int:
+    d = ctypes.c_int64()
+    _check(lib().tc_sector_dim(ctypes.byref(model.struct), int(k), ctypes.byref(d)),
+           "tc_sector_dim")
+    return d.value
+
+
+def tc_sector_states(model: Model, k: int):
+    """Basis indices of excitation sector k, increasing (numpy int64)."""
+    import numpy as np
+    out = np.zeros(tc_sector_dim(model, k), dtype=np.int64)
+    _check(lib().tc_sector_states(ctypes.byref(model.struct), int(k),
+                                  out.ctypes.data_as(ctypes.c_void_p)), "tc_sector_states")
+    return out
+
+
+def tc_sector_spectral_bounds(model: Model, k: int):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().tc_sector_spectral_bounds(ctypes.byref(model.struct), int(k), ctypes.byref(lo),
+                                           ctypes.byref(hi)), "tc_sector_spectral_bounds")
+    return lo.value, hi.value
+
+
+def tc_build_sector_hamiltonian(model: Model, k: int, H, stream=None):
+    """H: torch.float64 device tensor (d_k x ldh, row-major)."""
+    _check(lib().tc_build_sector_hamiltonian(ctypes.byref(model.struct), int(k), _ptr(H),
+                                             H.stride(0), _stream(stream)),
+           "tc_build_sector_hamiltonian")
+
+
+def tc_evolve_sector_workspace_size(instance, k: int, opts) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().tc_evolve_sector_workspace_size(ctypes.byref(instance), int(k),
+                                                 ctypes.byref(opts), ctypes.byref(b)),
+           "tc_evolve_sector_workspace_size")
+    return b.value
+
+
+def tc_evolve_sector(instance, k: int, opts, ws=None, device=None, stream=None):
+    """Steps one tc_instance whose matrices are the d_k x d_k blocks of sector k."""
+    if ws is None:
+        need = tc_evolve_sector_workspace_size(instance, k, opts)
+        ws = _workspace(need, device if device is not None else "cuda")
+    _check(lib().tc_evolve_sector(ctypes.byref(instance), int(k), ctypes.byref(opts), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "tc_evolve_sector")
 
 
 def tc_observables_workspace_size(N: int) -> int:

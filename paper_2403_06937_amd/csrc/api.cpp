@@ -147,6 +147,83 @@ int tc_spectral_bounds(const tc_model* m, double* lam_lo, double* lam_hi) {
   return TC_OK;
 }
 
+int tc_sector_dim(const tc_model* m, int32_t k, int64_t* d) {
+  clear_error();
+  ModelArgs a;
+  TC_RETURN_IF(make_model_args(m, &a));
+  TC_CHECK_ARG(d != nullptr, "d is NULL");
+  TC_CHECK_ARG(k >= 0 && k <= a.n + a.c, "sector k outside [0, n + c]");
+  int64_t cnt = 0;
+  for (int mm = std::max(0, k - a.n); mm <= std::min(k, a.c); ++mm) {
+    const int p = k - mm;
+    int64_t v = 1;
+    for (int q = 1; q <= p; ++q) v = v * (a.n - p + q) / q;   // C(n, p)
+    cnt += v;
+  }
+  *d = cnt;
+  return TC_OK;
+}
+
+int tc_sector_states(const tc_model* m, int32_t k, int64_t* states) {
+  clear_error();
+  int64_t d = 0;
+  TC_RETURN_IF(tc_sector_dim(m, k, &d));
+  TC_CHECK_ARG(states != nullptr || d == 0, "states is NULL");
+  const int n = m->n_atoms;
+  const int64_t N = int64_t(m->photon_cutoff + 1) << n;
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  int64_t i = 0;
+  for (int64_t s = 0; s < N; ++s)
+    if (int(s >> n) + __builtin_popcountll(uint64_t(s) & mask) == k) states[i++] = s;
+  return TC_OK;
+}
+
+int tc_sector_spectral_bounds(const tc_model* m, int32_t k, double* lam_lo, double* lam_hi) {
+  clear_error();
+  TC_CHECK_ARG(lam_lo != nullptr && lam_hi != nullptr, "output is NULL");
+  int64_t d = 0;
+  TC_RETURN_IF(tc_sector_dim(m, k, &d));
+  ModelArgs a;
+  TC_RETURN_IF(make_model_args(m, &a));
+  const int n = a.n;
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  double lo = INFINITY, hi = -INFINITY;
+  // a sector state couples only to states of its own sector, so the row
+  // radii of the full H are those of the block
+  for (int64_t s = 0; s < a.N; ++s) {
+    const int64_t mm = s >> n;
+    const uint64_t l = uint64_t(s) & mask;
+    if (int(mm) + __builtin_popcountll(l) != k) continue;
+    double centre = a.omega_c * double(mm), radius = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const bool ex = (l >> (n - 1 - i)) & 1;
+      if (ex) {
+        centre += a.omega_a[i];
+        if (mm < a.c) radius += std::fabs(a.g[i]) * std::sqrt(double(mm + 1));
+      } else if (mm > 0) {
+        radius += std::fabs(a.g[i]) * std::sqrt(double(mm));
+      }
+    }
+    lo = std::min(lo, centre - radius);
+    hi = std::max(hi, centre + radius);
+  }
+  *lam_lo = lo;
+  *lam_hi = hi;
+  return TC_OK;
+}
+
+int tc_build_sector_hamiltonian(const tc_model* m, int32_t k, double* H, int64_t ldh,
+                                void* stream) {
+  clear_error();
+  int64_t d = 0;
+  TC_RETURN_IF(tc_sector_dim(m, k, &d));
+  ModelArgs a;
+  TC_RETURN_IF(make_model_args(m, &a));
+  TC_CHECK_ARG(H != nullptr, "H is NULL");
+  TC_CHECK_ARG(ldh >= d, "ldh < d_k");
+  return launch_ham_sector(a, k, d, H, ldh, as_stream(stream));
+}
+
 int tc_build_hamiltonian(const tc_model* m, double* H, int64_t ldh, void* stream) {
   clear_error();
   ModelArgs a;

@@ -5,6 +5,7 @@
 // Reductions are deterministic: fixed per-thread strides, then a fixed LDS
 // tree inside one workgroup (no atomics), so reruns are bitwise identical.
 #include "kernels.h"
+#include "ham_entry.h"
 
 namespace tcm {
 namespace {
@@ -41,30 +42,10 @@ __device__ double block_max(double v, double* sh) {
 
 // ------------------------------------------------------------ Eq. (4)
 __global__ void ham_fill_kernel(ModelArgs m, double* __restrict__ H, int64_t ldh) {
-  const int n = m.n;
-  const uint64_t mask = (uint64_t(1) << n) - 1;
   const int64_t col = int64_t(blockIdx.x) * TPB + threadIdx.x;
   if (col >= m.N) return;
-  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y) {
-    const int64_t mr = row >> n, mc = col >> n;
-    const uint64_t lr = uint64_t(row) & mask, lc = uint64_t(col) & mask;
-    double v = 0.0;
-    if (row == col) {
-      v = m.omega_c * double(mr);
-      for (int i = 0; i < n; ++i)
-        if ((lr >> (n - 1 - i)) & 1) v += m.omega_a[i];
-    } else if (mr - mc == 1 || mc - mr == 1) {
-      // the state with fewer photons carries the one extra excited atom
-      const uint64_t llo = mr < mc ? lr : lc, lhi = mr < mc ? lc : lr;
-      const int64_t mhi = mr < mc ? mc : mr;
-      const uint64_t x = llo ^ lhi;
-      if (x != 0 && (x & (x - 1)) == 0 && (llo & x) != 0) {
-        const int bit = __ffsll((unsigned long long)x) - 1;
-        v = m.g[n - 1 - bit] * sqrt(double(mhi));
-      }
-    }
-    H[row * ldh + col] = v;
-  }
+  for (int64_t row = blockIdx.y; row < m.N; row += gridDim.y)
+    H[row * ldh + col] = ham_entry(m, row, col);
 }
 
 // ----------------------------------------------------- expm helpers
@@ -254,7 +235,8 @@ __global__ void damp_cavity_kernel(E* __restrict__ rho, int64_t ld, int n, int c
 
 // ------------------------------------------------------- per-step readout
 // map == NULL: rho is in the basis order; else basis state s sits at row and
-// column map[s] of rho (the excitation-sorted order of the sector stepper).
+// column map[s] of rho (the excitation-sorted order of the sector stepper, or
+// the order of one sector, where states outside it have map[s] = -1).
 template <typename E>
 __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t ld,
                                const int32_t* __restrict__ map,
@@ -268,6 +250,7 @@ __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t l
     double part = 0.0, ex = 0.0;
     for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
       const int64_t q = map ? int64_t(map[s]) : s;
+      if (q < 0) continue;                     // state outside a one-sector rho
       const double d = double(rho[q * ld + q].re);
       part += d;
       ex += double(popc64(uint64_t(s) & mask)) * d;

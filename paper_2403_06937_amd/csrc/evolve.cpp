@@ -33,6 +33,9 @@ struct InstPlan {
   // excitation-sector stepping (opts.sectors): rho and X in the sorted order
   // Each sector's positions are padded to a multiple of the product tile
   // (padding states hold exact zeros), so every block product is whole tiles.
+  // stepping within one excitation sector (tc_evolve_sector): rho, U are the
+  // d_k x d_k blocks; inv maps every basis state to its position or -1
+  int in_sector = -1;
   bool sectors = false;
   int64_t Np = 0;                    // padded dimension of the sorted order
   std::vector<int64_t> sdim;         // d_k: states of sector k
@@ -138,6 +141,7 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
     plan_sectors(o, ar, p);
     return;
   }
+  if (p->in_sector >= 0) p->inv = static_cast<int32_t*>(ar.take(size_t(m.N) * 4));
   if (o.gemm_mode == TC_GEMM_F64) {
     if (o.rho_dtype == TC_C128) {
       p->rho = in.rho; p->ldr = in.ldr; p->rho_converted = false;
@@ -296,7 +300,7 @@ int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_op
     TC_RETURN_IF(launch_copy_c64_to_c128(static_cast<const c64*>(p.rho), p.ldr,
                                          reinterpret_cast<c128*>(dst), p.N, p.N, p.N, s));
   }
-  if (o.frame == TC_FRAME_ROTATING && t != 0.0) {
+  if (o.frame == TC_FRAME_ROTATING && t != 0.0 && p.in_sector < 0) {
     if (o.rho_dtype == TC_C128)
       TC_RETURN_IF(launch_frame_phase_c128(p.m, reinterpret_cast<c128*>(dst), p.N, t, s));
     else
@@ -383,8 +387,22 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
   return TC_OK;
 }
 
+// One-sector run: position of every basis state in the sector's order (-1 outside).
+int upload_sector_map(InstPlan& p, hipStream_t s) {
+  const int n = p.m.n, k = p.in_sector;
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  std::vector<int32_t> map(p.m.N, -1);
+  int32_t pos = 0;
+  for (int64_t st = 0; st < p.m.N; ++st)
+    if (int(st >> n) + __builtin_popcountll(uint64_t(st) & mask) == k) map[st] = pos++;
+  TC_TRY_HIP(hipMemcpyAsync(p.inv, map.data(), map.size() * 4, hipMemcpyHostToDevice, s));
+  TC_TRY_HIP(hipStreamSynchronize(s));   // map is host memory of this call
+  return TC_OK;
+}
+
 int prepare(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
   if (p.sectors) return prepare_sectors(p, in, o, s);
+  if (p.in_sector >= 0) TC_RETURN_IF(upload_sector_map(p, s));
   TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
   // master state
   if (p.rho_converted) {
@@ -397,11 +415,19 @@ int prepare(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStre
   }
   // product operand
   const c128* U = reinterpret_cast<const c128*>(in.U);
+  // within one sector the frame factor e^{i w_c N dt} is the scalar e^{i w_c k dt}
+  const double ph = p.m.omega_c * double(p.in_sector) * o.dt;
   if (o.gemm_mode == TC_GEMM_F64) {
-    if (o.frame == TC_FRAME_ROTATING)
+    if (o.frame == TC_FRAME_ROTATING && p.in_sector >= 0)
+      TC_RETURN_IF(launch_phase_minus_identity_c128(U, in.ldu, std::cos(ph), std::sin(ph),
+                                                    static_cast<c128*>(p.op_own), p.ldop, p.N, s));
+    else if (o.frame == TC_FRAME_ROTATING)
       TC_RETURN_IF(launch_rotating_d(p.m, U, in.ldu, o.dt, static_cast<c128*>(p.op_own), p.ldop, s));
   } else {
-    if (o.frame == TC_FRAME_ROTATING)
+    if (o.frame == TC_FRAME_ROTATING && p.in_sector >= 0)
+      TC_RETURN_IF(launch_phase_minus_identity_c64(U, in.ldu, std::cos(ph), std::sin(ph),
+                                                   static_cast<c64*>(p.op_own), p.ldop, p.N, s));
+    else if (o.frame == TC_FRAME_ROTATING)
       TC_RETURN_IF(launch_rotating_d_c64(p.m, U, in.ldu, o.dt, static_cast<c64*>(p.op_own), p.ldop, s));
     else
       TC_RETURN_IF(launch_copy_c128_to_c64(U, in.ldu, static_cast<c64*>(p.op_own), p.ldop, p.N, p.N, s));
@@ -426,7 +452,8 @@ int finish(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStrea
     }
     return TC_OK;
   }
-  if (o.frame == TC_FRAME_ROTATING && T != 0.0) {
+  // (one sector: the frame's phase is global, e^{i w_c k t} rho e^{-i w_c k t} = rho)
+  if (o.frame == TC_FRAME_ROTATING && T != 0.0 && p.in_sector < 0) {
     if (o.gemm_mode == TC_GEMM_F64)
       TC_RETURN_IF(launch_frame_phase_c128(p.m, static_cast<c128*>(p.rho), p.ldr, T, s));
     else
@@ -694,6 +721,66 @@ int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o, v
                   std::to_string(b) + ")");
         return TC_ERR_NONFINITE;
       }
+    }
+  }
+  return TC_OK;
+}
+
+int tc_evolve_sector_workspace_size(const tc_instance* inst, int32_t k, const tc_evolve_opts* o,
+                                    size_t* bytes) {
+  clear_error();
+  TC_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+  TC_CHECK_ARG(inst != nullptr, "instance is NULL");
+  TC_RETURN_IF(validate_opts(o));
+  TC_CHECK_ARG(o->sectors == 0, "sectors must be 0 for a one-sector run");
+  int64_t d = 0;
+  TC_RETURN_IF(tc_sector_dim(inst->model, k, &d));
+  ModelArgs m;
+  TC_RETURN_IF(make_model_args(inst->model, &m));
+  if (m.kappa > 0.0 || m.gamma > 0.0) {
+    set_error("the damping channels lead out of an excitation sector");
+    return TC_ERR_UNSUPPORTED;
+  }
+  TC_CHECK_ARG(inst->N == d, "instance N != d_k of the sector");
+  TC_CHECK_ARG(inst->U != nullptr && inst->rho != nullptr, "U / rho is NULL");
+  TC_CHECK_ARG(inst->ldu >= d && inst->ldr >= d, "leading dimension < d_k");
+  if (inst->pop_out || inst->photon_dist_out)
+    TC_CHECK_ARG(o->record_every >= 1, "record_every must be >= 1 when records are requested");
+  if (inst->checkpoints)
+    TC_CHECK_ARG(o->checkpoint_every >= 1, "checkpoint_every must be >= 1 with checkpoints");
+  Arena ar(nullptr, 0);
+  InstPlan p;
+  p.in_sector = k;
+  plan_instance(*inst, *o, m, ar, &p);
+  *bytes = ar.used;
+  return TC_OK;
+}
+
+int tc_evolve_sector(const tc_instance* inst, int32_t k, const tc_evolve_opts* o, void* ws,
+                     size_t ws_bytes, void* stream) {
+  clear_error();
+  size_t need = 0;
+  TC_RETURN_IF(tc_evolve_sector_workspace_size(inst, k, o, &need));
+  TC_CHECK_ARG(ws != nullptr || need == 0, "workspace is NULL");
+  if (ws_bytes < need) {
+    set_error("workspace too small for tc_evolve_sector: need " + std::to_string(need) + " bytes");
+    return TC_ERR_WORKSPACE;
+  }
+  hipStream_t s = as_stream(stream);
+  ModelArgs m;
+  TC_RETURN_IF(make_model_args(inst->model, &m));
+  Arena ar(ws, ws_bytes);
+  InstPlan p;
+  p.in_sector = k;
+  plan_instance(*inst, *o, m, ar, &p);
+  TC_RETURN_IF(evolve_one(p, *inst, *o, s));
+  if (o->renorm_every > 0 && o->steps >= o->renorm_every) {
+    double flag = 0.0;
+    TC_TRY_HIP(hipMemcpyAsync(&flag, p.scratch + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    TC_TRY_HIP(hipStreamSynchronize(s));
+    if (flag != 0.0) {
+      set_error("renormalisation found a non-finite or non-positive trace");
+      return TC_ERR_NONFINITE;
     }
   }
   return TC_OK;

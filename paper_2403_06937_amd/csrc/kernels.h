@@ -120,6 +120,16 @@ int launch_mirror_lower_c128(c128* rho, int64_t ld, int64_t N, const int32_t* se
                              hipStream_t s);
 int launch_mirror_lower_c64(c64* rho, int64_t ld, int64_t N, const int32_t* sec, hipStream_t s);
 
+// ---- one excitation sector (sectors.hip)
+// H_k[i][j] = H[s_i][s_j] (Eq. (4)) over the d states s_0 < s_1 < ... of sector k.
+int launch_ham_sector(const ModelArgs& m, int k, int64_t d, double* H, int64_t ldh,
+                      hipStream_t s);
+// out = ph * U - I (N x N, ph = (ph_re, ph_im)).
+int launch_phase_minus_identity_c128(const c128* U, int64_t ldu, double ph_re, double ph_im,
+                                     c128* out, int64_t ldo, int64_t N, hipStream_t s);
+int launch_phase_minus_identity_c64(const c128* U, int64_t ldu, double ph_re, double ph_im,
+                                    c64* out, int64_t ldo, int64_t N, hipStream_t s);
+
 // bfloat16 hi/lo split of binary32 values.
 int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -9,6 +9,7 @@
 // Position i holds basis state perm[i] (-1 for padding) of sector sec[i];
 // basis state s sits at position inv[s].
 #include "kernels.h"
+#include "ham_entry.h"
 
 namespace tcm {
 namespace {
@@ -84,6 +85,69 @@ __global__ void mirror_lower_kernel(E* __restrict__ rho, int64_t ld, int64_t N,
   }
 }
 
+// The i-th basis state (increasing index) of excitation sector k: photon
+// numbers m from max(0, k - n) upward, and within one m the n-bit atom
+// patterns with k - m ones in increasing order (combinatorial unranking,
+// binom[a * (n + 1) + b] = C(a, b)).  -1 if i >= d_k.
+__device__ int64_t sector_state(int64_t i, int k, int n, int c, const int64_t* binom) {
+  const int mlo = k - n > 0 ? k - n : 0, mhi = k < c ? k : c;
+  for (int m = mlo; m <= mhi; ++m) {
+    int p = k - m;
+    const int64_t cnt = binom[n * (n + 1) + p];
+    if (i < cnt) {
+      uint64_t l = 0;
+      for (int b = n - 1; b >= 0; --b) {
+        // patterns whose bit b is 0 place all p ones among the b lower bits
+        const int64_t c0 = p <= b ? binom[b * (n + 1) + p] : 0;
+        if (i >= c0) { l |= uint64_t(1) << b; i -= c0; --p; }
+      }
+      return (int64_t(m) << n) | int64_t(l);
+    }
+    i -= cnt;
+  }
+  return -1;
+}
+
+// H_k[i][j] = H[state_i][state_j] over the d_k states of sector k.
+__global__ void ham_sector_kernel(ModelArgs m, int k, int64_t d, double* __restrict__ H,
+                                  int64_t ldh) {
+  __shared__ int64_t binom[(TC_MAX_ATOMS + 1) * (TC_MAX_ATOMS + 1)];
+  const int n = m.n;
+  for (int e = threadIdx.x; e < (n + 1) * (n + 1); e += TPB) {
+    const int a = e / (n + 1), b = e % (n + 1);
+    int64_t v = 0;
+    if (b <= a) {
+      v = 1;
+      for (int q = 1; q <= b; ++q) v = v * (a - b + q) / q;
+    }
+    binom[e] = v;
+  }
+  __syncthreads();
+  const int64_t j = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (j >= d) return;
+  const int64_t sj = sector_state(j, k, n, m.c, binom);
+  for (int64_t i = blockIdx.y; i < d; i += gridDim.y)
+    H[i * ldh + j] = ham_entry(m, sector_state(i, k, n, m.c, binom), sj);
+}
+
+// out = ph * U - I (the rotating-frame operand of one sector, where the frame
+// factor e^{i w_c N dt} is the scalar e^{i w_c k dt}).
+template <typename Eout>
+__global__ void phase_minus_identity_kernel(const c128* __restrict__ U, int64_t ldu, double ph_re,
+                                            double ph_im, Eout* __restrict__ out, int64_t ldo,
+                                            int64_t N) {
+  typedef typename real_of<Eout>::type T;
+  const int64_t j = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (j >= N) return;
+  for (int64_t i = blockIdx.y; i < N; i += gridDim.y) {
+    const c128 v = U[i * ldu + j];
+    double re = ph_re * v.re - ph_im * v.im;
+    const double im = ph_re * v.im + ph_im * v.re;
+    if (i == j) re -= 1.0;
+    out[i * ldo + j] = Eout{T(re), T(im)};
+  }
+}
+
 template <typename Ein, typename Eout>
 int gather_impl(const Ein* src, int64_t lds, const int32_t* map, int64_t ro, int64_t co,
                 int64_t rows, int64_t cols, double ph_re, double ph_im, bool sub, Eout* dst,
@@ -107,7 +171,36 @@ int mirror_impl(E* rho, int64_t ld, int64_t N, const int32_t* sec, hipStream_t s
   return TC_OK;
 }
 
+template <typename Eout>
+int phase_minus_identity_impl(const c128* U, int64_t ldu, double ph_re, double ph_im, Eout* out,
+                              int64_t ldo, int64_t N, hipStream_t s) {
+  if (N <= 0) return TC_OK;
+  const dim3 grid(unsigned((N + TPB - 1) / TPB), unsigned(N < 4096 ? N : 4096));
+  hipLaunchKernelGGL(phase_minus_identity_kernel<Eout>, grid, dim3(TPB), 0, s, U, ldu, ph_re,
+                     ph_im, out, ldo, N);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
 }  // namespace
+
+int launch_ham_sector(const ModelArgs& m, int k, int64_t d, double* H, int64_t ldh,
+                      hipStream_t s) {
+  if (d <= 0) return TC_OK;
+  const dim3 grid(unsigned((d + TPB - 1) / TPB), unsigned(d < 4096 ? d : 4096));
+  hipLaunchKernelGGL(ham_sector_kernel, grid, dim3(TPB), 0, s, m, k, d, H, ldh);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int launch_phase_minus_identity_c128(const c128* U, int64_t ldu, double ph_re, double ph_im,
+                                     c128* out, int64_t ldo, int64_t N, hipStream_t s) {
+  return phase_minus_identity_impl(U, ldu, ph_re, ph_im, out, ldo, N, s);
+}
+int launch_phase_minus_identity_c64(const c128* U, int64_t ldu, double ph_re, double ph_im,
+                                    c64* out, int64_t ldo, int64_t N, hipStream_t s) {
+  return phase_minus_identity_impl(U, ldu, ph_re, ph_im, out, ldo, N, s);
+}
 
 int launch_gather_c128_c128(const c128* src, int64_t lds, const int32_t* map, int64_t ro,
                             int64_t co, int64_t rows, int64_t cols, double ph_re, double ph_im,

@@ -11,8 +11,9 @@ from __future__ import annotations
 import torch
 
 from . import (Model, TC_C128, TC_C64, TC_EXPM_SS_TAYLOR, TC_FRAME_LAB, TC_GEMM_F64,
-               make_instance, make_opts, tc_build_hamiltonian, tc_evolve, tc_expm,
-               tc_observables, tc_spectral_bounds)
+               make_instance, make_opts, tc_build_hamiltonian, tc_build_sector_hamiltonian,
+               tc_evolve, tc_evolve_sector, tc_expm, tc_observables, tc_sector_dim,
+               tc_sector_spectral_bounds, tc_spectral_bounds)
 
 
 def model_of(inst) -> Model:
@@ -61,6 +62,50 @@ def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: flo
                      full_product=int(full_product), sectors=int(sectors))
     inst = make_instance(model, U, rho, pop, pd, ck)
     tc_evolve([inst], opts, ws=ws, device=rho.device)
+    return pop, pd, ck
+
+
+def sector_hamiltonian(model: Model, k: int, device="cuda") -> torch.Tensor:
+    """The d_k x d_k block of Eq. (4) on excitation sector k (the paper's 2^n
+    model for c >= n, k = n)."""
+    d = tc_sector_dim(model, k)
+    H = torch.empty((d, d), dtype=torch.float64, device=device)
+    tc_build_sector_hamiltonian(model, k, H)
+    return H
+
+
+def sector_propagator(model: Model, k: int, dt: float, method: int = TC_EXPM_SS_TAYLOR,
+                      device="cuda", H: torch.Tensor = None):
+    """(H_k, U_k) with U_k = exp(-i H_k dt) (or Eq. (10)'s series) on the device."""
+    if H is None:
+        H = sector_hamiltonian(model, k, device)
+    lo, hi = tc_sector_spectral_bounds(model, k)
+    U = torch.empty(H.shape, dtype=torch.complex128, device=device)
+    tc_expm(H, dt, lo, hi, U, method)
+    return H, U
+
+
+def evolve_sector(model: Model, k: int, U: torch.Tensor, rho: torch.Tensor, steps: int,
+                  dt: float, gemm_mode: int = TC_GEMM_F64, frame: int = TC_FRAME_LAB,
+                  renorm_every: int = 0, record_every: int = 1, checkpoint_every: int = 0,
+                  record_photons: bool = False, ws=None, full_product: bool = False):
+    """Steps the d_k x d_k block rho of sector k in place; returns the records
+    as evolve() does."""
+    rho_dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
+    R = steps // record_every + 1 if record_every else 0
+    pop = torch.zeros(R, dtype=torch.float64, device=rho.device) if R else None
+    pd = (torch.zeros((R, model.c + 1), dtype=torch.float64, device=rho.device)
+          if (R and record_photons) else None)
+    ck = None
+    if checkpoint_every:
+        ck = torch.empty((steps // checkpoint_every + 1,) + tuple(rho.shape), dtype=rho.dtype,
+                         device=rho.device)
+    opts = make_opts(steps, dt, gemm_mode, rho_dtype, frame, renorm_every,
+                     record_every if record_every else 0, checkpoint_every,
+                     full_product=int(full_product))
+    inst = make_instance(model, U, rho, pop, pd, ck)
+    inst.N = rho.shape[0]
+    tc_evolve_sector(inst, k, opts, ws=ws, device=rho.device)
     return pop, pd, ck
 
 

@@ -184,6 +184,22 @@ def workload_grad8() -> Workload:
                     description="n=8 atoms, cutoff 8, N=2304, adjoint gradient")
 
 
+def workload_paper(n: int) -> Workload:
+    """The paper's own runs (Sec. IV): n atoms, all excited, no photons, on the
+    2^n states of its atom-only model, which is the excitation-n sector of
+    the cavity model with cutoff c = n.  The paper states neither couplings,
+    detunings nor dt; the seeded draws follow the N = 5120 workload
+    (g_i ~ U(0.005, 0.02), delta_i ~ N(0, 0.005), dt = 0.05)."""
+    rng = _rng(600 + n)
+    g = rng.uniform(0.005, 0.02, n)
+    delta = rng.normal(0.0, 0.005, n)
+    inst = Instance(n=n, c=n, g=g, omega_a=1.0 + delta,
+                    psi0=basis_state(n, n, 0, [1] * n))
+    return Workload(f"tcm_paper_n{n}_N{1 << n}", [inst], dt=0.05, steps=0,
+                    description=f"paper's 2^n model, n={n} atoms all excited",
+                    extra={"sector": n})
+
+
 WORKLOADS = {
     "jc3": workload_jc3,
     "n9": workload_n9,

@@ -199,3 +199,49 @@ def test_sector_option_validation_and_workspace():
     Np = sum(D)
     need = 2 * Np * Np * 16 + sum(x * x for x in D) * 16 + 2 * Np * 4 + N * 4
     assert need <= ws <= need + 64 * 1024
+
+
+def test_sector_entry_points_host_side():
+    """tc_sector_dim / tc_sector_states against the oracle's sectors; the
+    one-sector workspace query refuses a Lindblad model, a wrong N and
+    opts.sectors, and sizes the block's buffers plus the state map."""
+    from oracle import model as omodel
+    n, c = 4, 3
+    m = tcm.Model(n, c, [0.01] * n, [1.0] * n)
+    secs = omodel.sectors(n, c)
+    for k in range(n + c + 1):
+        assert tcm.tc_sector_dim(m, k) == secs[k].size
+        assert np.array_equal(tcm.tc_sector_states(m, k), secs[k])
+    for k in (-1, n + c + 1):
+        with pytest.raises(tcm.TcmError):
+            tcm.tc_sector_dim(m, k)
+
+    class Fake:
+        def __init__(self, p, ld):
+            self.p, self.ld = p, ld
+
+        def data_ptr(self):
+            return self.p
+
+        def stride(self, i):
+            return self.ld
+
+    d = secs[3].size
+    inst = tcm.make_instance(m, Fake(0x1000, d), Fake(0x2000, d))
+    inst.N = d
+    ws = tcm.tc_evolve_sector_workspace_size(inst, 3, tcm.make_opts(10, 0.1))
+    assert ws >= d * d * 16 + m.N * 4
+    inst.N = d + 1
+    with pytest.raises(tcm.TcmError) as e:
+        tcm.tc_evolve_sector_workspace_size(inst, 3, tcm.make_opts(10, 0.1))
+    assert e.value.code == tcm.TC_ERR_INVALID_ARGUMENT
+    inst.N = d
+    with pytest.raises(tcm.TcmError) as e:
+        tcm.tc_evolve_sector_workspace_size(inst, 3, tcm.make_opts(10, 0.1, sectors=1))
+    assert e.value.code == tcm.TC_ERR_INVALID_ARGUMENT
+    mo = tcm.Model(n, c, [0.01] * n, [1.0] * n, kappa=0.1)
+    inst2 = tcm.make_instance(mo, Fake(0x1000, d), Fake(0x2000, d))
+    inst2.N = d
+    with pytest.raises(tcm.TcmError) as e:
+        tcm.tc_evolve_sector_workspace_size(inst2, 3, tcm.make_opts(10, 0.1))
+    assert e.value.code == tcm.TC_ERR_UNSUPPORTED

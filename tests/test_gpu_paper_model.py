@@ -1,0 +1,173 @@
+"""One excitation sector on the GPU (tc_build_sector_hamiltonian,
+tc_evolve_sector): the blocks of Eq. (4) and, with c >= n and k = n, the
+paper's own 2^n model of Sec. II, stepped with Eq. (10)'s ten-term series
+(Sec. III.B) and with the exact propagator, against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import tcm_inputs as ti
+from oracle import evolve as oev
+from oracle import model as omodel
+
+pytestmark = pytest.mark.gpu
+
+tcm = pytest.importorskip("paper_2403_06937_amd")
+from paper_2403_06937_amd import pipeline  # noqa: E402
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    tcm.lib()
+
+
+def _paper_index(n):
+    """Sector-order position of each atom pattern l of the paper's model: the
+    sector lists basis indices (n - |l|) 2^n + l in increasing order."""
+    idx = [(n - bin(l).count("1")) * (1 << n) + l for l in range(1 << n)]
+    order = np.argsort(idx)                  # position -> pattern
+    return np.array(idx), order
+
+
+@pytest.mark.parametrize("n,c,seed", [(3, 3, 0), (4, 2, 1), (5, 6, 2), (1, 4, 3), (6, 0, 4)])
+def test_sector_blocks_and_states(n, c, seed):
+    """Every block H_k equals the oracle's H restricted to sector k, with the
+    states in increasing basis index; the Gershgorin interval holds the block's
+    spectrum."""
+    inst = ti.random_model(n, c, seed)
+    m = pipeline.model_of(inst)
+    H = omodel.hamiltonian(n, c, inst.g, inst.omega_a)
+    secs = omodel.sectors(n, c)
+    assert sorted(secs) == list(range(n + c + 1))
+    for k, idx in secs.items():
+        assert tcm.tc_sector_dim(m, k) == idx.size
+        assert np.array_equal(tcm.tc_sector_states(m, k), idx)
+        Hk = pipeline.sector_hamiltonian(m, k).cpu().numpy()
+        assert np.max(np.abs(Hk - H[np.ix_(idx, idx)])) < 1e-15, k
+        lo, hi = tcm.tc_sector_spectral_bounds(m, k)
+        ev = np.linalg.eigvalsh(H[np.ix_(idx, idx)])
+        assert lo <= ev.min() + 1e-12 and ev.max() <= hi + 1e-12
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_paper_model_taylor10(n):
+    """The paper's model (c = n, k = n, N = 2^n) from all atoms excited, with
+    L of Eq. (10) and R = L^dag stepped 60 times in FP64: the GPU's L and
+    every population record against the oracle's own ten-term series and
+    Eq. (12) product L (rho R)."""
+    inst = ti.random_model(n, n, 10 + n)
+    m = pipeline.model_of(inst)
+    dt, steps = 0.05, 60
+    _, L = pipeline.sector_propagator(m, n, dt, tcm.TC_EXPM_TAYLOR10)
+    idx, order = _paper_index(n)
+    Hp = omodel.paper_model_hamiltonian(n, inst.g, inst.omega_a)
+    Lo, Ro = oev.taylor_factors(Hp, dt)
+    Lg = L.cpu().numpy()
+    assert np.max(np.abs(Lg - Lo[np.ix_(order, order)])) < 1e-13
+    # all excited: pattern l = 2^n - 1, basis index 2^n - 1 (no photons), the
+    # first position of the sector
+    D = 1 << n
+    p0 = int(np.nonzero(order == D - 1)[0][0])
+    assert p0 == 0
+    rho0 = np.zeros((D, D), dtype=complex)
+    rho0[p0, p0] = 1.0
+    rho = torch.from_numpy(rho0).to("cuda")
+    pop, _, _ = pipeline.evolve_sector(m, n, L, rho, steps, dt)
+    exc = np.array([bin(l).count("1") for l in range(D)], dtype=float)
+    r = np.zeros((D, D), dtype=complex)
+    r[D - 1, D - 1] = 1.0                    # pattern order: all excited is l = 2^n - 1
+    ref = []
+    for s in range(steps + 1):
+        ref.append(float(np.sum(exc * np.real(np.diag(r)))))
+        if s < steps:
+            r = oev.taylor_step(Lo, Ro, r)
+    popn = pop.cpu().numpy()
+    assert np.max(np.abs(popn - np.array(ref))) < 1e-12
+    out = rho.cpu().numpy()
+    assert np.max(np.abs(out - r[np.ix_(order, order)])) < 1e-12
+
+
+@pytest.mark.parametrize("mode,frame,dtype,tol", [
+    (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 1e-10),
+    (tcm.TC_GEMM_F64, tcm.TC_FRAME_ROTATING, torch.complex128, 1e-10),
+    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5)])
+@pytest.mark.parametrize("n,c,k", [(4, 4, 4), (6, 3, 4), (8, 8, 8)])
+def test_sector_run_against_exact(mode, frame, dtype, tol, n, c, k):
+    """A Gaussian random pure state on sector k, 100 steps with the exact
+    propagator, renormalised every 20: final block and populations against
+    the oracle's eigendecomposition of the block."""
+    inst = ti.random_model(n, c, 20 + n)
+    inst.g = inst.g * 10
+    m = pipeline.model_of(inst)
+    dt, steps = 0.05, 100
+    idx = omodel.sectors(n, c)[k]
+    Hk = omodel.hamiltonian(n, c, inst.g, inst.omega_a)[np.ix_(idx, idx)]
+    rng = np.random.default_rng([ti.SEED_ROOT, 800 + n])
+    psi = ti.gaussian_state(idx.size, rng)
+    _, U = pipeline.sector_propagator(m, k, dt)
+    rho = torch.from_numpy(np.outer(psi, psi.conj())).to("cuda").to(dtype)
+    pop, pd, _ = pipeline.evolve_sector(m, k, U, rho, steps, dt, mode, frame, 20,
+                                        record_photons=True)
+    W = oev.propagator(Hk, steps * dt)
+    psiT = W @ psi
+    ref = np.outer(psiT, psiT.conj())
+    err = float(np.max(np.abs(rho.cpu().numpy().astype(np.complex128) - ref)))
+    exc = np.array([bin(int(s) & ((1 << n) - 1)).count("1") for s in idx], dtype=float)
+    perr = abs(float(pop[-1].item()) - float(np.sum(exc * np.abs(psiT) ** 2)))
+    photons = np.array([int(s) >> n for s in idx])
+    pdist = np.array([np.sum(np.abs(psiT[photons == mm]) ** 2) for mm in range(c + 1)])
+    derr = float(np.max(np.abs(pd[-1].cpu().numpy() - pdist)))
+    print(f"sector run n={n} c={c} k={k} mode={mode} frame={frame}: max-entry {err:.2e}, "
+          f"population {perr:.2e}, photon distribution {derr:.2e}")
+    assert err < tol and perr < tol and derr < tol
+
+
+def test_sector_run_equals_full_space_block():
+    """The one-sector run equals the full-space run (c = n) restricted to the
+    sector, for a state that lives in it (FP64, to rounding)."""
+    n = 5
+    inst = ti.random_model(n, n, 31, state="excited")
+    inst.g = inst.g * 10
+    m = pipeline.model_of(inst)
+    dt, steps = 0.05, 50
+    _, U = pipeline.propagator(m, dt)
+    full = torch.from_numpy(inst.rho0()).to("cuda")
+    pf, _, _ = pipeline.evolve(m, U, full, steps, dt)
+    idx = omodel.sectors(n, n)[n]
+    _, Uk = pipeline.sector_propagator(m, n, dt)
+    blk = torch.from_numpy(inst.rho0()[np.ix_(idx, idx)]).to("cuda")
+    pk, _, _ = pipeline.evolve_sector(m, n, Uk, blk, steps, dt)
+    f = full.cpu().numpy()
+    assert np.max(np.abs(f[np.ix_(idx, idx)] - blk.cpu().numpy())) < 1e-13
+    assert np.max(np.abs(pf.cpu().numpy() - pk.cpu().numpy())) < 1e-13
+
+
+def test_paper_model_n10_split_bf16():
+    """The paper's model at n = 10 (N = 1024), all excited, 200 split-BF16
+    steps in the sector's rotating frame: within 1e-5 of the exact evolution."""
+    n = 10
+    w = ti.get("n9")
+    rng = np.random.default_rng([ti.SEED_ROOT, 910])
+    g = rng.uniform(0.005, 0.02, n)
+    wa = 1.0 + rng.normal(0.0, 0.005, n)
+    m = tcm.Model(n, n, list(g), list(wa))
+    dt, steps = w.dt, 200
+    _, U = pipeline.sector_propagator(m, n, dt)
+    D = 1 << n
+    idx, order = _paper_index(n)
+    rho = torch.zeros((D, D), dtype=torch.complex64, device="cuda")
+    rho[0, 0] = 1.0                           # all excited: first sector position
+    pop, _, _ = pipeline.evolve_sector(m, n, U, rho, steps, dt, tcm.TC_GEMM_SPLIT_BF16,
+                                       tcm.TC_FRAME_ROTATING, 20)
+    Hp = omodel.paper_model_hamiltonian(n, g, wa)
+    psi0 = np.zeros(D, dtype=complex)
+    psi0[-1] = 1.0
+    psiT = oev.propagator(Hp, steps * dt) @ psi0
+    ref = np.outer(psiT, psiT.conj())[np.ix_(order, order)]
+    err = float(np.max(np.abs(rho.cpu().numpy().astype(np.complex128) - ref)))
+    exc = np.array([bin(l).count("1") for l in range(D)], dtype=float)
+    perr = abs(float(pop[-1].item()) - float(np.sum(exc * np.abs(psiT) ** 2)))
+    print(f"paper model n=10 split-bf16: max-entry {err:.2e}, population {perr:.2e}")
+    assert err < 1e-5 and perr < 1e-5

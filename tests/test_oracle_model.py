@@ -102,3 +102,34 @@ def test_c_zero_is_diagonal():
     inst = ti.random_model(3, 0, 9)
     H = model.hamiltonian(3, 0, inst.g, inst.omega_a)
     assert np.count_nonzero(H - np.diag(np.diagonal(H))) == 0
+
+
+def test_paper_model_is_the_excitation_n_sector():
+    """The paper's 2^n model written on atom patterns equals the excitation-n
+    block of the (c >= n) Kronecker-built H, state for state (each pattern l
+    is the basis state (n - |l|) 2^n + l); n = 1 is the Jaynes-Cummings 2 x 2
+    block [[w_c, g], [g, w_a]] in the order (|1 photon, g>, |0, e>)."""
+    for n, c, seed in [(1, 1, 0), (2, 2, 1), (3, 4, 2), (4, 4, 3), (5, 6, 4)]:
+        inst = ti.random_model(n, c, seed)
+        Hp = model.paper_model_hamiltonian(n, inst.g, inst.omega_a, 1.3)
+        H = model.hamiltonian(n, c, inst.g, inst.omega_a, 1.3)
+        idx = [(n - bin(l).count("1")) * (1 << n) + l for l in range(1 << n)]
+        assert sorted(idx) == sorted(model.sectors(n, c)[n].tolist())
+        assert np.max(np.abs(Hp - H[np.ix_(idx, idx)])) < 1e-15
+    g, wa = 0.013, 1.02
+    Hp = model.paper_model_hamiltonian(1, [g], [wa], 0.97)
+    assert np.allclose(Hp, [[0.97, g], [g, wa]], rtol=0, atol=1e-17)
+
+
+def test_paper_model_equal_g_dicke_chain():
+    """Equal g at resonance: the all-excited start stays in the symmetric
+    states |m>|D_{n-m}>, whose chain couplings are g (m + 1) sqrt(n - m); the
+    chain's eigenvalues are eigenvalues of the paper's 2^n model."""
+    n, g = 4, 0.02
+    Hp = model.paper_model_hamiltonian(n, [g] * n, [1.0] * n, 1.0)
+    chain = np.diag([float(n)] * (n + 1))
+    for m in range(n):
+        chain[m, m + 1] = chain[m + 1, m] = g * (m + 1) * np.sqrt(n - m)
+    ev = np.linalg.eigvalsh(Hp)
+    for lam in np.linalg.eigvalsh(chain):
+        assert np.min(np.abs(ev - lam)) < 1e-14
