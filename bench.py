@@ -324,7 +324,9 @@ def bench_sectors11(tcm, pipeline, ti, steps=40):
     for key, mode, frame, dtype, kind in (
             ("fp64", tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, tcm.TC_KERNEL_GEMM_F64),
             ("fp32", tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64,
-             tcm.TC_KERNEL_GEMM_F32)):
+             tcm.TC_KERNEL_GEMM_F32),
+            ("split", tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64,
+             tcm.TC_KERNEL_SPLIT_BF16)):
         rho = torch.from_numpy(inst.rho0()).to("cuda").to(dtype)
         pipeline.evolve(m, U, rho.clone(), 2, dt, mode, frame, w.renorm_every, sectors=True)
         torch.cuda.synchronize()
@@ -337,8 +339,8 @@ def bench_sectors11(tcm, pipeline, ti, steps=40):
         kms, kl = tcm.tc_profile_read(kind)
         tcm.tc_profile_enable(False)
         ms = e0.elapsed_time(e1) / steps
-        peak = PEAK_F64 if key == "fp64" else PEAK_F32
-        q = 128 if tcm.tc_autotune_query(mode, N) == 1 else 64
+        peak = {"fp64": PEAK_F64, "fp32": PEAK_F32, "split": PEAK_BF16}[key]
+        q = 128 if (key == "split" or tcm.tc_autotune_query(mode, N) == 1) else 64
         fx = sector_executed_flop_per_step(inst.n, inst.c, q)
         out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
                     "tflops": fl / (ms * 1e-3) / 1e12,
@@ -348,6 +350,9 @@ def bench_sectors11(tcm, pipeline, ti, steps=40):
                     "product_frac_of_peak": (fl / 2.0) / (kms / max(1, kl) * 1e-3) / peak,
                     "product_executed_frac_of_peak":
                         (fx / 2.0) / (kms / max(1, kl) * 1e-3) / peak,
+                    "product_issued_frac_of_peak":
+                        (3.0 if key == "split" else 1.0) * (fx / 2.0)
+                        / (kms / max(1, kl) * 1e-3) / peak,
                     "final_excitation": float(torch.real(torch.diagonal(rho)).sum().item())}
         del rho
     del U

@@ -47,6 +47,11 @@ struct InstPlan {
   void* blocks = nullptr;            // U_k (lab) or D_k = e^{i w_c k dt} U_k - I (rotating)
   char* items = nullptr;             // descriptors of the two grouped products
   GroupedProducts g1, g2;
+  // split-BF16 by sectors: planes of each block (op and conj(op)^T), of X
+  // (rows) and of rho hat^T (rows = columns of rho hat), Np x Np
+  std::vector<Planes4> sopA, sopB;
+  Planes4 sXp, sRt;
+  SplitGrouped sg1, sg2;
 };
 
 int validate_opts(const tc_evolve_opts* o) {
@@ -61,10 +66,6 @@ int validate_opts(const tc_evolve_opts* o) {
   TC_CHECK_ARG(o->checkpoint_every >= 0, "checkpoint_every < 0");
   TC_CHECK_ARG(std::isfinite(o->dt), "dt not finite");
   TC_CHECK_ARG(o->sectors == 0 || o->sectors == 1, "sectors must be 0 or 1");
-  if (o->sectors && o->gemm_mode == TC_GEMM_SPLIT_BF16) {
-    set_error("sector stepping runs TC_GEMM_F64 or TC_GEMM_F32 products");
-    return TC_ERR_UNSUPPORTED;
-  }
   return TC_OK;
 }
 
@@ -100,8 +101,10 @@ void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
   const int64_t N = p->N;
   const bool f64 = o.gemm_mode == TC_GEMM_F64;
   const size_t eb = f64 ? 16 : 8;
-  // pad to the edge of the grouped product's tile (128 or 64)
-  const int64_t q = tile_variant_for(N, f64) == 1 ? 128 : 64;
+  // pad to the edge of the grouped product's tile (128 or 64; the split
+  // product's tile is 128)
+  const bool split = o.gemm_mode == TC_GEMM_SPLIT_BF16;
+  const int64_t q = split ? SPLIT_BM : (tile_variant_for(N, f64) == 1 ? 128 : 64);
   p->sectors = true;
   std::vector<int64_t> off;
   sector_sizes(p->m.n, p->m.c, p->sdim, off);
@@ -126,7 +129,17 @@ void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
   p->perm = static_cast<int32_t*>(ar.take(size_t(pos) * 4));
   p->inv = static_cast<int32_t*>(ar.take(size_t(N) * 4));
   p->secpos = static_cast<int32_t*>(ar.take(size_t(pos) * 4));
-  p->items = static_cast<char*>(ar.take(2 * grouped_bytes(ns)));
+  p->items = static_cast<char*>(ar.take(2 * (split ? split_grouped_bytes(ns) : grouped_bytes(ns))));
+  if (split) {
+    p->sopA.resize(ns);
+    p->sopB.resize(ns);
+    for (int k = 0; k < ns; ++k) {
+      p->sopA[k] = split_take_planes(ar, p->spd[k], p->spd[k]);
+      p->sopB[k] = split_take_planes(ar, p->spd[k], p->spd[k]);
+    }
+    p->sXp = split_take_planes(ar, pos, pos);
+    p->sRt = split_take_planes(ar, pos, pos);
+  }
 }
 
 // Lays out (or sizes, when ar.base == nullptr) the workspace of one instance.
@@ -237,7 +250,11 @@ int dissipate(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
       TC_RETURN_IF(launch_dissipation_c128(p.m, static_cast<c128*>(p.X), p.N, o.dt, s));
     else
       TC_RETURN_IF(launch_dissipation_c64(p.m, static_cast<c64*>(p.X), p.N, o.dt, s));
-    return permute_from(p, o, p.X, p.N, md, s);
+    TC_RETURN_IF(permute_from(p, o, p.X, p.N, md, s));
+    if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
+      TC_RETURN_IF(split_matrix(static_cast<const c64*>(p.rho), p.ldr, p.Np, p.Np, true, false,
+                                p.sRt, s));
+    return TC_OK;
   }
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_dissipation_c128(p.m, static_cast<c128*>(p.rho), p.ldr, o.dt, s);
@@ -253,7 +270,10 @@ int renorm(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_renorm_c128(static_cast<c128*>(p.rho), p.ldr, n, p.scratch, s);
   TC_RETURN_IF(launch_renorm_c64(static_cast<c64*>(p.rho), p.ldr, n, p.scratch, s));
-  if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16 && p.sectors)
+    TC_RETURN_IF(split_matrix(static_cast<const c64*>(p.rho), p.ldr, p.Np, p.Np, true, false,
+                              p.sRt, s));
+  else if (o.gemm_mode == TC_GEMM_SPLIT_BF16)
     TC_RETURN_IF(split_state(static_cast<const c64*>(p.rho), p.ldr, p.N, p.planes, s));
   return TC_OK;
 }
@@ -312,6 +332,51 @@ int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_op
 // Sector stepping: sorted order, blocks of U (or D), and the descriptors of
 // the two grouped products of a step (largest sectors first, so the
 // persistent launch starts on the longest tiles).
+// Split-BF16 by sectors: planes of every block and of rho hat^T, then the two
+// grouped split products of a step,
+//   X_{k,k:} = U_k rho_{k,k:}   (rotating: + rho_{k,k:}), planes of X written by rows
+//   rho'_{:k,k} = X_{:k,k} U_k^dag (rotating: + X_{:k,k}), planes of rho'^T written
+// with K offsets at sector starts (multiples of 128).
+int prepare_sector_split(InstPlan& p, const tc_evolve_opts& o, const std::vector<int>& order,
+                         hipStream_t s) {
+  const int64_t Np = p.Np;
+  const bool rot = o.frame == TC_FRAME_ROTATING;
+  c64* rho = static_cast<c64*>(p.rho);
+  c64* X = static_cast<c64*>(p.X);
+  for (size_t k = 0; k < p.spd.size(); ++k) {
+    const c64* blk = static_cast<const c64*>(p.blocks) + p.boff[k];
+    const int64_t d = p.spd[k];
+    TC_RETURN_IF(split_matrix(blk, d, d, d, false, false, p.sopA[k], s));
+    TC_RETURN_IF(split_matrix(blk, d, d, d, true, true, p.sopB[k], s));
+  }
+  TC_TRY_HIP(hipMemsetAsync(p.sXp.base, 0, size_t(4) * p.sXp.rows * p.sXp.ld * 2, s));
+  TC_RETURN_IF(split_matrix(rho, p.ldr, Np, Np, true, false, p.sRt, s));
+  std::vector<SplitProduct> d1, d2;
+  for (int k : order) {
+    const int64_t off = p.spo[k], d = p.spd[k];
+    SplitProduct g1;                    // X_{k, k:} = op_k rho_{k, k:}
+    g1.A = p.sopA[k].base; g1.lda = p.sopA[k].ld;
+    g1.B = p.sRt.base + plane_offset(p.sRt.ld, off, off, 0); g1.ldb = p.sRt.ld;
+    g1.M = d; g1.N = Np - off; g1.Kp = d;
+    if (rot) { g1.br = 1.f; g1.Cin = rho + off * p.ldr + off; g1.ldcin = p.ldr; }
+    g1.Cf = X + off * p.ldx + off; g1.ldcf = p.ldx;
+    g1.P = p.sXp.base + plane_offset(p.sXp.ld, off, off, 0); g1.ldp = p.sXp.ld;
+    SplitProduct g2;                    // rho'_{:k, k} = X_{:k, k} op_k^dag
+    g2.A = p.sXp.base + plane_offset(p.sXp.ld, 0, off, 0); g2.lda = p.sXp.ld;
+    g2.B = p.sopB[k].base; g2.ldb = p.sopB[k].ld;
+    g2.M = off + d; g2.N = d; g2.Kp = d;
+    if (rot) { g2.br = 1.f; g2.Cin = X + off; g2.ldcin = p.ldx; }
+    g2.Cf = rho + off; g2.ldcf = p.ldr;
+    g2.P = p.sRt.base + plane_offset(p.sRt.ld, off, 0, 0); g2.ldp = p.sRt.ld; g2.p_trans = true;
+    d1.push_back(g1);
+    d2.push_back(g2);
+  }
+  const int ns = int(p.spd.size());
+  TC_RETURN_IF(split_grouped_build(d1, p.items, &p.sg1, s));
+  TC_RETURN_IF(split_grouped_build(d2, p.items + split_grouped_bytes(ns), &p.sg2, s));
+  return TC_OK;
+}
+
 int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
   TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
   const int64_t N = p.N, Np = p.Np;
@@ -358,6 +423,7 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
   for (int k = 0; k < ns; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return p.spd[a] > p.spd[b]; });
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16) return prepare_sector_split(p, o, order, s);
   auto at = [&](void* base, int64_t r, int64_t c, int64_t ld) {
     return static_cast<void*>(static_cast<char*>(base) + (size_t(r) * size_t(ld) + size_t(c)) * eb);
   };
@@ -471,6 +537,10 @@ int finish(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStrea
 }
 
 int step(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
+  if (p.sectors && o.gemm_mode == TC_GEMM_SPLIT_BF16) {
+    TC_RETURN_IF(split_grouped_run(p.sg1, s));
+    return split_grouped_run(p.sg2, s);
+  }
   if (p.sectors) {
     TC_RETURN_IF(grouped_run(p.g1, s));
     return grouped_run(p.g2, s);

@@ -2,6 +2,8 @@
 // values hi = rne(x), lo = rne(x - hi); a real product a*b is formed as
 // hi_a hi_b + hi_a lo_b + lo_a hi_b on BF16 MFMA with FP32 accumulation.
 #pragma once
+#include <vector>
+
 #include "common.h"
 #include "gemm_mfma.h"
 
@@ -46,6 +48,39 @@ int split_state(const c64* rho, int64_t ld, int64_t N, const SplitPlanes& p, hip
 // and mirrors it.
 int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotating, bool herm,
                const SplitPlanes& p, hipStream_t s);
+
+// Planes of rows x ld bf16 (ld a multiple of SPLIT_BK) carved from a workspace.
+Planes4 split_take_planes(Arena& ar, int64_t rows, int64_t ld);
+// All P.rows x P.ld entries of P from the c64 matrix src (R x C valid, element
+// (r, c) at src[r*ld + c], or src[c*ld + r] when trans), conjugated if conj,
+// zero outside.
+int split_matrix(const c64* src, int64_t ld, int64_t R, int64_t C, bool trans, bool conj,
+                 const Planes4& P, hipStream_t s);
+
+// Split products of whole 128 x 128 tiles launched together, one workgroup
+// per tile (the excitation-sector blocks of a step).  A and B point at the
+// product's first row and K offset inside 4-plane operands (K offsets are
+// multiples of SPLIT_BK); the result goes to any of the FP32 Cf and the hi/lo
+// planes P (row-major, or transposed when p_trans), as in step_split.
+struct SplitProduct {
+  const uint16_t* A = nullptr; int64_t lda = 0;   // lda, ldb, ldp: padded K extents of the planes
+  const uint16_t* B = nullptr; int64_t ldb = 0;
+  int64_t M = 0, N = 0, Kp = 0;
+  float ar = 1.f, ai = 0.f, br = 0.f, bi = 0.f;   // alpha, beta
+  const c64* Cin = nullptr; int64_t ldcin = 0;
+  c64* Cf = nullptr; int64_t ldcf = 0;
+  uint16_t* P = nullptr; int64_t ldp = 0; bool p_trans = false;
+};
+struct SplitGrouped {
+  int count = 0;
+  int total_tiles = 0;
+  void* items_dev = nullptr;
+};
+size_t split_grouped_bytes(int count);
+// Uploads the descriptors (synchronises s).
+int split_grouped_build(const std::vector<SplitProduct>& ps, void* items_dev, SplitGrouped* g,
+                        hipStream_t s);
+int split_grouped_run(const SplitGrouped& g, hipStream_t s);
 
 // General split product on c64 operands (kernel-level entry point).
 struct SplitGemmPlan {

@@ -45,6 +45,34 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 
+// Global-memory accesses through address-space-1 pointers of scalar or vector
+// type: the grouped kernel reads its operand pointers from a descriptor array,
+// where the compiler could not otherwise tell them from LDS and would issue
+// flat accesses (which the LDS barrier's lgkmcnt wait would also wait for).
+typedef float f2v __attribute__((ext_vector_type(2), aligned(4)));
+__device__ __forceinline__ u4 gld_u4(const void* p) {
+  typedef __attribute__((address_space(1))) const u4 G;
+  return *(G*)p;
+}
+__device__ __forceinline__ c64 gld_c64(const c64* p) {
+  typedef __attribute__((address_space(1))) const f2v G;
+  const f2v v = *(G*)p;
+  return c64{v.x, v.y};
+}
+__device__ __forceinline__ void gst_c64(c64* p, float re, float im) {
+  typedef __attribute__((address_space(1))) f2v G;
+  *(G*)p = f2v{re, im};
+}
+__device__ __forceinline__ void gst_u2(uint16_t* p, u2 v) {
+  typedef u2 u2a __attribute__((aligned(4)));
+  typedef __attribute__((address_space(1))) u2a G;
+  *(G*)p = v;
+}
+__device__ __forceinline__ void gst_u16(uint16_t* p, uint16_t v) {
+  typedef __attribute__((address_space(1))) uint16_t G;
+  *(G*)p = v;
+}
+
 __device__ __forceinline__ uint16_t rne_bf16(float x) {
   const uint32_t b = __float_as_uint(x);
   if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu) != 0)
@@ -152,7 +180,7 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
         float yi = p.ar * xi + p.ai * xr;
         const bool inb = row < p.M && col < p.N;
         if (use_beta && inb) {
-          const c64 c = p.cin_trans ? p.Cin[col * p.ldcin + row] : p.Cin[row * p.ldcin + col];
+          const c64 c = gld_c64(p.Cin + (p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col));
           yr += p.br * c.re - p.bi * c.im;
           yi += p.br * c.im + p.bi * c.re;
         }
@@ -160,8 +188,8 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
         vr[r] = yr;
         vi[r] = yi;
         if (p.Cf && inb) {
-          p.Cf[row * p.ldcf + col] = c64{yr, yi};
-          if (mirror) p.Cf[col * p.ldcf + row] = c64{yr, -yi};
+          gst_c64(p.Cf + row * p.ldcf + col, yr, yi);
+          if (mirror) gst_c64(p.Cf + col * p.ldcf + row, yr, -yi);
         }
       }
       if (p.P) {
@@ -181,7 +209,7 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
             const uint32_t m = (PL_IH == q || PL_IL == q) ? f : 0;
             const u2 v = u2{(uint32_t(h[q][0]) | (uint32_t(h[q][1]) << 16)) ^ (m | (m << 16)),
                             (uint32_t(h[q][2]) | (uint32_t(h[q][3]) << 16)) ^ (m | (m << 16))};
-            *reinterpret_cast<u2*>(p.P + plane_offset(p.ldp, col, row0, q)) = v;
+            gst_u2(p.P + plane_offset(p.ldp, col, row0, q), v);
           }
         }
         if (!p.p_trans || mirror) {
@@ -190,7 +218,8 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
           for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              p.P[plane_offset(p.ldp, row0 + r, col, q)] = h[q][r] ^ (flip ? neg[q] : 0);
+              gst_u16(p.P + plane_offset(p.ldp, row0 + r, col, q),
+                      uint16_t(h[q][r] ^ (flip ? neg[q] : 0)));
         }
       }
     }
@@ -211,26 +240,23 @@ __device__ __forceinline__ void sync_lds() {
 // from the registers into the LDS buffer freed by the last barrier and the
 // registers are refilled with tile t + 2 before the products, so a load has a
 // whole iteration to arrive and the barrier waits for no global load.
+typedef u4 SplitLds[2][4][SPLIT_BM][4];
+
 template <int WGM, int WGN, int WM, int WN>
-__global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const SplitParams p) {
+__device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn, SplitLds& sA,
+                                           SplitLds& sB) {
   constexpr int NT = 64 * WGM * WGN;
   static_assert(16 * WM * WGM == SPLIT_BM && 16 * WN * WGN == SPLIT_BN, "128 x 128 tile");
+  static_assert(SPLIT_BM == SPLIT_BN, "square tile");
   static_assert(NT == 256 || NT == 512, "staging pattern");
   // a tile of one operand is 128 rows x 256 bytes (four planes of 32 bf16):
   // 2048 chunks; thread t moves chunk t % 16 of rows t / 16 + h NT / 16
   constexpr int RPT = 2048 / NT;        // chunks per thread and operand
-  __shared__ u4 sA[2][4][SPLIT_BM][4];
-  __shared__ u4 sB[2][4][SPLIT_BN][4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  int tm, tn;
-  if (p.herm)
-    tri_coords(xcd_linear(blockIdx.x, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
-  else
-    tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = int64_t(tm) * SPLIT_BM, n0 = int64_t(tn) * SPLIT_BN;
 
   // Each K tile of a row is 256 contiguous bytes, so a wave's load covers
@@ -252,8 +278,8 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
     for (int h = 0; h < RPT; ++h) {
       const char* ga = reinterpret_cast<const char*>(baseA + h * (NT / 16) * rsa + k0);
       const char* gb = reinterpret_cast<const char*>(baseB + h * (NT / 16) * rsb + k0);
-      st[h] = *reinterpret_cast<const u4*>(ga + offA);
-      st[RPT + h] = *reinterpret_cast<const u4*>(gb + offB);
+      st[h] = gld_u4(ga + offA);
+      st[RPT + h] = gld_u4(gb + offB);
     }
   };
   auto store = [&](const u4 (&st)[2 * RPT], int buf) {
@@ -330,6 +356,44 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
 
   split_epilogue<WM, WN>(p, acc_re, acc_im, m0 + wm * WM * 16, n0 + wn * WN * 16,
                          p.herm && tm != tn);
+}
+
+template <int WGM, int WGN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const SplitParams p) {
+  __shared__ SplitLds sA, sB;
+  int tm, tn;
+  if (p.herm)
+    tri_coords(xcd_linear(blockIdx.x, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  else
+    tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
+  split_tile<WGM, WGN, WM, WN>(p, tm, tn, sA, sB);
+}
+
+// Many split products in one launch, one workgroup per tile of the
+// concatenated tile list (item i's tiles start at tile_begin; no Hermitian
+// items): the excitation-sector blocks of one step.
+struct SplitItem {
+  SplitParams p;
+  int tile_begin;
+};
+
+template <int WGM, int WGN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WGM * WGN, 1)
+split_grouped_kernel(const SplitItem* __restrict__ items, int count) {
+  __shared__ SplitLds sA, sB;
+  const int t = blockIdx.x;
+  int lo = 0, hi = count - 1;              // last item with tile_begin <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+  }
+  const SplitParams p = items[lo].p;
+  const int local = t - items[lo].tile_begin;
+  const int per_group = GROUP_M * p.tiles_n;
+  const int first_m = (local / per_group) * GROUP_M;
+  const int gsize = min(p.tiles_m - first_m, GROUP_M);
+  const int in_group = local % per_group;
+  split_tile<WGM, WGN, WM, WN>(p, first_m + in_group % gsize, in_group / gsize, sA, sB);
 }
 
 // out(r, c) for r < Rp, c < Cp from src (R x C valid, element (r, c) at
@@ -437,6 +501,62 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
 }
 
 }  // namespace
+
+Planes4 split_take_planes(Arena& ar, int64_t rows, int64_t ld) { return take_planes(ar, rows, ld); }
+
+int split_matrix(const c64* src, int64_t ld, int64_t R, int64_t C, bool trans, bool conj,
+                 const Planes4& P, hipStream_t s) {
+  return split_into(src, ld, R, C, trans, conj, P, s);
+}
+
+size_t split_grouped_bytes(int count) { return size_t(count) * sizeof(SplitItem); }
+
+int split_grouped_build(const std::vector<SplitProduct>& ps, void* items_dev, SplitGrouped* g,
+                        hipStream_t s) {
+  std::vector<SplitItem> items;
+  int64_t t = 0;
+  for (const SplitProduct& d : ps) {
+    if (d.M % SPLIT_BM != 0 || d.N % SPLIT_BN != 0 || d.Kp % SPLIT_BK != 0 || d.Kp <= 0 ||
+        d.M <= 0 || d.N <= 0) {
+      set_error("grouped split products take whole 128 x 128 tiles and a K extent of 32s");
+      return TC_ERR_INVALID_ARGUMENT;
+    }
+    SplitItem it;
+    SplitParams& q = it.p;
+    q.A = d.A; q.lda = d.lda;
+    q.B = d.B; q.ldb = d.ldb;
+    q.M = d.M; q.N = d.N; q.Kp = d.Kp;
+    q.ar = d.ar; q.ai = d.ai; q.br = d.br; q.bi = d.bi;
+    q.Cin = d.Cin; q.ldcin = d.ldcin; q.cin_trans = 0;
+    q.Cf = d.Cf; q.ldcf = d.ldcf;
+    q.P = d.P; q.ldp = d.ldp; q.p_trans = d.p_trans ? 1 : 0;
+    q.herm = 0;
+    q.tiles_m = int(d.M / SPLIT_BM);
+    q.tiles_n = int(d.N / SPLIT_BN);
+    it.tile_begin = int(t);
+    t += int64_t(q.tiles_m) * q.tiles_n;
+    items.push_back(it);
+  }
+  if (t > (int64_t(1) << 30)) { set_error("too many tiles in one group"); return TC_ERR_UNSUPPORTED; }
+  g->count = int(items.size());
+  g->total_tiles = int(t);
+  g->items_dev = items_dev;
+  if (!items.empty()) {
+    TC_TRY_HIP(hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(SplitItem),
+                              hipMemcpyHostToDevice, s));
+    TC_TRY_HIP(hipStreamSynchronize(s));   // items is host memory of this call
+  }
+  return TC_OK;
+}
+
+int split_grouped_run(const SplitGrouped& g, hipStream_t s) {
+  if (g.count == 0 || g.total_tiles == 0) return TC_OK;
+  ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
+  hipLaunchKernelGGL((split_grouped_kernel<2, 4, 4, 2>), dim3(unsigned(g.total_tiles)), dim3(512),
+                     0, s, static_cast<const SplitItem*>(g.items_dev), g.count);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
 
 void split_plan(Arena& ar, int64_t N, SplitPlanes* p) {
   const int64_t Np = round_up(N, SPLIT_BM);   // SPLIT_BM = SPLIT_BN, multiple of SPLIT_BK

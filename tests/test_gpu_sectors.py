@@ -1,8 +1,8 @@
 """Excitation-sector block stepping (tc_evolve with opts.sectors = 1) on the
 GPU: against the oracle's dense evolution and against the dense GPU products,
-on ragged sizes, in FP64 and FP32, both frames, with records, checkpoints,
-renormalisation and the Lindblad term; plus the degenerate cases (no cavity
-photons, one atom, zero steps)."""
+on ragged sizes, both frames, with records, checkpoints,
+renormalisation and the Lindblad term, in FP64, FP32 and split-BF16; plus
+the degenerate cases (no cavity photons, one atom, zero steps)."""
 import numpy as np
 import pytest
 import torch
@@ -22,6 +22,7 @@ MODES = [
     (tcm.TC_GEMM_F64, tcm.TC_FRAME_ROTATING, torch.complex128, 1e-10),
     (tcm.TC_GEMM_F32, tcm.TC_FRAME_LAB, torch.complex64, 1e-5),
     (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
 ]
 
 
@@ -124,7 +125,8 @@ def test_checkpoints_and_hermiticity():
 
 @pytest.mark.parametrize("mode,frame,dtype,tol", [
     (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 1e-12),
-    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 2e-5)])
+    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 2e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 2e-5)])
 def test_open_system(mode, frame, dtype, tol):
     """With the Lindblad term (kappa = 0.05, gamma = 0.03) each sector step is
     followed by the damping channels in the basis order: equal to the oracle's
@@ -185,12 +187,18 @@ def test_workload_n9_sectors():
     assert err < 1e-10
 
 
-def test_split_mode_is_rejected():
-    inst = ti.random_model(3, 2, 14)
-    m = pipeline.model_of(inst)
-    _, U = pipeline.propagator(m, 0.05)
-    rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
-    with pytest.raises(tcm.TcmError) as e:
-        pipeline.evolve(m, U, rho, 2, 0.05, tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING,
-                        sectors=True)
-    assert e.value.code == tcm.TC_ERR_UNSUPPORTED
+def test_split_lab_frame_runs():
+    """Split-BF16 by sectors in the lab frame (the rounded operand is U_k, not
+    D_k): same result as the dense split products in the lab frame to the
+    lab frame's error level."""
+    inst = ti.random_model(5, 3, 15)          # N = 128
+    inst.g = inst.g * 20
+    dt, steps = 0.05, 40
+    ref, _, _ = _oracle(inst, dt, steps)
+    a, _, _, _ = _gpu(inst, dt, steps, tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_LAB,
+                      torch.complex64, True, renorm=10)
+    b, _, _, _ = _gpu(inst, dt, steps, tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_LAB,
+                      torch.complex64, False, renorm=10)
+    ea, eb = float(np.max(np.abs(a - ref))), float(np.max(np.abs(b - ref)))
+    print(f"split lab frame: sectors {ea:.2e}, dense {eb:.2e}")
+    assert ea < 1e-3 and eb < 1e-3

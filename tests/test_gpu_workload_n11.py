@@ -109,7 +109,8 @@ def test_propagator_sampled_entries(setup):
 
 @pytest.mark.parametrize("mode,dtype,frame,tol", [
     (tcm.TC_GEMM_F64, torch.complex128, tcm.TC_FRAME_LAB, 1e-10),
-    (tcm.TC_GEMM_F32, torch.complex64, tcm.TC_FRAME_ROTATING, 1e-5)])
+    (tcm.TC_GEMM_F32, torch.complex64, tcm.TC_FRAME_ROTATING, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, torch.complex64, tcm.TC_FRAME_ROTATING, 1e-5)])
 def test_sector_blocks_full_run(setup, mode, dtype, frame, tol):
     """All 200 steps by excitation-sector blocks (opts.sectors = 1, the
     launch configuration bench.py times for this form): every entry of the
