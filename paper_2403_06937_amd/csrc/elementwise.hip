@@ -233,6 +233,51 @@ __global__ void damp_cavity_kernel(E* __restrict__ rho, int64_t ld, int n, int c
   }
 }
 
+// The same channel with each chain held in registers (c + 1 <= L): a thread
+// owns the (c + 1)^2 elements of one (a, a') pair and walks its 2c + 1
+// chains, so every element is read once and written once and a workgroup
+// touches only the c + 1 rows of one a.
+template <typename E, int L>
+__global__ void damp_cavity_reg_kernel(E* __restrict__ rho, int64_t ld, int n, int c,
+                                       double eta) {
+  const int64_t per = int64_t(1) << n;
+  const int64_t ac = int64_t(blockIdx.x) * TPB + threadIdx.x;   // column atom index a'
+  if (ac >= per) return;
+  const double q = 1.0 - eta, se = sqrt(eta);
+  for (int64_t ar = blockIdx.y; ar < per; ar += gridDim.y) {
+    for (int d = -c; d <= c; ++d) {                              // m' - m
+      const int mlo = d < 0 ? -d : 0;
+      const int len = c + 1 - (d < 0 ? -d : d);
+      double xr[L], xi[L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        if (j < len) {
+          const E x = rho[(int64_t(mlo + j) * per + ar) * ld + int64_t(mlo + j + d) * per + ac];
+          xr[j] = double(x.re);
+          xi[j] = double(x.im);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        if (j >= len) continue;
+        const int m = mlo + j, mp = m + d;
+        double coef = 1.0;                     // eta^{(m + m')/2}
+        for (int e = 0; e < m + mp; ++e) coef *= se;
+        double yr = 0.0, yi = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          if (j + l >= len) break;
+          if (l > 0) coef *= sqrt(double(m + l) * double(mp + l)) / double(l) * q;
+          yr += coef * xr[j + l];
+          yi += coef * xi[j + l];
+        }
+        rho[(int64_t(m) * per + ar) * ld + int64_t(mp) * per + ac] =
+            E{decltype(E::re)(yr), decltype(E::re)(yi)};
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------- per-step readout
 // map == NULL: rho is in the basis order; else basis state s sits at row and
 // column map[s] of rho (the excitation-sorted order of the sector stepper, or
@@ -701,8 +746,12 @@ int launch_dissipation_t(const ModelArgs& m, E* rho, int64_t ld, double dt, hipS
     const int64_t per = int64_t(1) << m.n;
     const dim3 grid(unsigned((per + TPB - 1) / TPB), unsigned(per < 4096 ? per : 4096),
                     unsigned(2 * m.c + 1));
-    hipLaunchKernelGGL(damp_cavity_kernel<E>, grid, dim3(TPB), 0, s, rho, ld, m.n, m.c,
-                       exp(-m.kappa * dt));
+    if (m.c + 1 <= 8)
+      hipLaunchKernelGGL((damp_cavity_reg_kernel<E, 8>), dim3(grid.x, grid.y), dim3(TPB), 0, s,
+                         rho, ld, m.n, m.c, exp(-m.kappa * dt));
+    else
+      hipLaunchKernelGGL(damp_cavity_kernel<E>, grid, dim3(TPB), 0, s, rho, ld, m.n, m.c,
+                         exp(-m.kappa * dt));
     TC_TRY_HIP(hipGetLastError());
   }
   return TC_OK;

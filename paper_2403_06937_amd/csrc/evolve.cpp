@@ -579,7 +579,7 @@ int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipS
 // device counter), and with use_graph the launches of a chunk of steps are
 // captured once in a hipGraph and replayed.
 struct BatchBufs {
-  char* items = nullptr;          // 4 groups of count GroupItem descriptors
+  char* items = nullptr;          // 8 groups of count GroupItem descriptors
   ReadoutItem* ritems = nullptr;  // count readout descriptors
   int* counter = nullptr;         // record index
 };
@@ -589,7 +589,7 @@ bool use_batched(int count, const tc_evolve_opts& o) {
 }
 
 void plan_batch(Arena& ar, int count, BatchBufs* b) {
-  b->items = static_cast<char*>(ar.take(4 * grouped_bytes(count)));
+  b->items = static_cast<char*>(ar.take(8 * grouped_bytes(count)));
   b->ritems = static_cast<ReadoutItem*>(ar.take(size_t(count) * sizeof(ReadoutItem)));
   b->counter = static_cast<int*>(ar.take(sizeof(int)));
 }
@@ -618,23 +618,29 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
   const bool f64 = o.gemm_mode == TC_GEMM_F64;
   for (int b = 0; b < count; ++b) TC_RETURN_IF(prepare(plans[b], inst[b], o, s));
   // group the products by tile shape (autotuner table per dimension bucket)
-  std::vector<GemmDesc> d1[3], d2[3];
+  // and by whether N is a multiple of the tile: those run one workgroup per
+  // tile with the unchecked tile (fewer registers), the rest persistently
+  std::vector<GemmDesc> d1[3][2], d2[3][2];
   for (int b = 0; b < count; ++b) {
     GemmDesc g1, g2;
     step_descs(plans[b], o, g1, g2);
     const int v = tile_variant_for(plans[b].N, f64);
-    d1[v].push_back(g1);
-    d2[v].push_back(g2);
+    const int edge = v == 1 ? 128 : 64;
+    const int e = plans[b].N % edge == 0 ? 0 : 1;
+    d1[v][e].push_back(g1);
+    d2[v][e].push_back(g2);
   }
-  GroupedProducts G1[3], G2[3];
+  GroupedProducts G1[3][2], G2[3][2];
   char* it = bb.items;
-  for (int v = 1; v <= 2; ++v) {
-    if (d1[v].empty()) continue;
-    TC_RETURN_IF(grouped_build(d1[v], f64, v, it, &G1[v], s));
-    it += grouped_bytes(count);
-    TC_RETURN_IF(grouped_build(d2[v], f64, v, it, &G2[v], s));
-    it += grouped_bytes(count);
-  }
+  for (int v = 1; v <= 2; ++v)
+    for (int e = 0; e < 2; ++e) {
+      if (d1[v][e].empty()) continue;
+      TC_RETURN_IF(grouped_build(d1[v][e], f64, v, it, &G1[v][e], s));
+      it += grouped_bytes(count);
+      TC_RETURN_IF(grouped_build(d2[v][e], f64, v, it, &G2[v][e], s));
+      it += grouped_bytes(count);
+      G1[v][e].persistent = G2[v][e].persistent = e == 1;
+    }
   bool rec = false, ckpt = false;
   std::vector<ReadoutItem> ri(count);
   for (int b = 0; b < count; ++b) {
@@ -660,8 +666,10 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
     if (inst[b].checkpoints) TC_RETURN_IF(copy_checkpoint(plans[b], inst[b], o, 0, 0.0, s));
 
   auto one_step = [&](int64_t st, hipStream_t q) -> int {
-    for (int v = 1; v <= 2; ++v) TC_RETURN_IF(grouped_run(G1[v], q));
-    for (int v = 1; v <= 2; ++v) TC_RETURN_IF(grouped_run(G2[v], q));
+    for (int v = 1; v <= 2; ++v)
+      for (int e = 0; e < 2; ++e) TC_RETURN_IF(grouped_run(G1[v][e], q));
+    for (int v = 1; v <= 2; ++v)
+      for (int e = 0; e < 2; ++e) TC_RETURN_IF(grouped_run(G2[v][e], q));
     for (int b = 0; b < count; ++b) TC_RETURN_IF(dissipate(plans[b], o, q));
     if (o.renorm_every > 0 && st % o.renorm_every == 0)
       for (int b = 0; b < count; ++b) TC_RETURN_IF(renorm(plans[b], o, q));

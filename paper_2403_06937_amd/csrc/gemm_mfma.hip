@@ -455,9 +455,9 @@ grouped_gemm_kernel(const GroupItem* __restrict__ items, int count, XcdSplit xs)
 }
 
 // One workgroup per tile of the concatenated list (every product a multiple
-// of the tile): no loop state across tiles, so the register count is that of
-// the one-product kernel, and the hardware hands out tiles as CUs free up
-// (the list is ordered by decreasing K, longest tiles first).
+// of the tile; a Hermitian product walks its upper tile triangle and mirrors):
+// no loop state across tiles, so the register count is that of the
+// one-product kernel, and the hardware hands out tiles as CUs free up.
 template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
           int PADB>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
@@ -472,12 +472,19 @@ grouped_tile_kernel(const GroupItem* __restrict__ items, int count) {
   }
   const Params p = items[lo].p;
   const int local = t - items[lo].tile_begin;
-  const int per_group = GROUP_M * p.tiles_n;
-  const int first_m = (local / per_group) * GROUP_M;
-  const int gsize = min(p.tiles_m - first_m, GROUP_M);
-  const int in_group = local % per_group;
-  gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(
-      p, first_m + in_group % gsize, in_group / gsize, false, lds);
+  int tm, tn;
+  if (p.herm) {
+    tri_coords(local, p.tiles_m, tm, tn);
+  } else {
+    const int per_group = GROUP_M * p.tiles_n;
+    const int first_m = (local / per_group) * GROUP_M;
+    const int gsize = min(p.tiles_m - first_m, GROUP_M);
+    const int in_group = local % per_group;
+    tm = first_m + in_group % gsize;
+    tn = in_group / gsize;
+  }
+  gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, p.herm && tm != tn,
+                                                               lds);
 }
 
 // Tile shapes (BM, BN, BKT, WM, WN); the wave count is (BM/16WM)(BN/16WN).
