@@ -24,8 +24,10 @@
 // the end of the loading iteration 25.2 ms; 4 waves of 64 x 64: 29.5 ms.
 // A variant with one wave per SIMD (128 x 32 outputs each, accumulators in
 // AGPRs) that reads its B fragments straight from global memory ran at 31 ms.
-// 16-byte chunks are XOR-swizzled by row so that the 16 rows a wave reads at
-// one K offset hit distinct LDS banks.  Tile order as in the FP64 kernel:
+// 16-byte chunks are XOR-swizzled by row and the planes padded so that
+// neither the fragment reads nor the staged stores conflict on LDS banks
+// (SQ_LDS_BANK_CONFLICT: 0; with unpadded planes the stores conflicted, 29 %
+// of the LDS cycles).  Tile order as in the FP64 kernel:
 // XCD-contiguous ranges walked in groups of 8 tile rows; a Hermitian result
 // walks the upper tile triangle only.
 //
@@ -91,7 +93,15 @@ __device__ __forceinline__ f4 mma(const u4& a, const u4& b, f4 c) {
                                                  __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
+// LDS bank conflicts of 16-byte accesses (measured with SQ_LDS_BANK_CONFLICT
+// on gfx950): lanes are served 8 at a time over 32 banks of 4 bytes, so 8
+// lanes are conflict-free when their 16-byte addresses are distinct modulo 8.
+// A plane holds 128 rows of four 16-byte chunks; the chunk of row r is XORed
+// with (r >> 1) & 3, which spreads the 8 consecutive rows of a fragment read
+// over the 8 positions, and each plane is padded by four chunks, so that a
+// store's 8 lanes (two planes of one row) land on distinct positions too.
 __device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+constexpr int LDS_PLANE = SPLIT_BM * 4 + 4;     // 16-byte chunks per padded plane
 
 // Plane operands are in the interleaved layout of Planes4; lda, ldb and ldp
 // are their padded K extents (the row stride is four times that).
@@ -240,7 +250,8 @@ __device__ __forceinline__ void sync_lds() {
 // from the registers into the LDS buffer freed by the last barrier and the
 // registers are refilled with tile t + 2 before the products, so a load has a
 // whole iteration to arrive and the barrier waits for no global load.
-typedef u4 SplitLds[2][4][SPLIT_BM][4];
+typedef u4 SplitLds[2][4][LDS_PLANE];
+#define LDS_AT(buf, q, row, chunk) [buf][q][(row) * 4 + (chunk)]
 
 template <int WGM, int WGN, int WM, int WN>
 __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn, SplitLds& sA,
@@ -265,6 +276,7 @@ __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn,
   const int64_t rsa = 4 * p.lda, rsb = 4 * p.ldb;     // row strides
   const int srow = tid >> 4, sc = tid & 15;
   const int sq = sc >> 2, sw = (sc & 3) ^ swz(srow);  // swz(srow + 16 h) == swz(srow)
+  static_assert(NT / 16 % 4 == 0, "the staged rows of one thread share their swizzle");
   // workgroup-uniform bases and one 32-bit per-lane byte offset per operand
   // (rows below 128 of at most 2^23 bf16), so each load is a uniform base plus
   // a lane offset
@@ -285,8 +297,8 @@ __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn,
   auto store = [&](const u4 (&st)[2 * RPT], int buf) {
 #pragma unroll
     for (int h = 0; h < RPT; ++h) {
-      sA[buf][sq][srow + (NT / 16) * h][sw] = st[h];
-      sB[buf][sq][srow + (NT / 16) * h][sw] = st[RPT + h];
+      sA LDS_AT(buf, sq, srow + (NT / 16) * h, sw) = st[h];
+      sB LDS_AT(buf, sq, srow + (NT / 16) * h, sw) = st[RPT + h];
     }
   };
 
@@ -308,14 +320,14 @@ __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn,
     for (int j = 0; j < WN; ++j) {
       const int row = (wn * WN + j) * 16 + lr;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) b[j][q] = sB[buf][q][row][lc ^ swz(row)];
+      for (int q = 0; q < 4; ++q) b[j][q] = sB LDS_AT(buf, q, row, lc ^ swz(row));
     }
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
       const int row = (wm * WM + i) * 16 + lr;
       u4 a[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = sA[buf][q][row][lc ^ swz(row)];
+      for (int q = 0; q < 4; ++q) a[q] = sA LDS_AT(buf, q, row, lc ^ swz(row));
       const u4 nih = a[PL_IH] ^ sgn, nil = a[PL_IL] ^ sgn;
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
