@@ -166,36 +166,44 @@ def bench_batch64(tcm, pipeline, ti, steps=50):
 
 def bench_grad8(tcm, pipeline, ti):
     """n=8, c=8 (N=2304): complex64 forward with checkpoints every 50 (500 steps,
-    rotating frame) and the adjoint sweep (FP32 products, FP64 Frechet)."""
+    rotating frame) and the adjoint sweep (FP32 products, FP64 Frechet), with
+    dense products and by excitation sectors."""
     import torch
     w = ti.get("grad8")
     inst = w.instances[0]
     m = pipeline.model_of(inst)
     H, U = pipeline.propagator(m, w.dt)
-    rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    pipeline.evolve(m, U, rho.clone(), 4, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING)  # warm-up
-    torch.cuda.synchronize()
-    ev[0].record()
-    _, _, ck = pipeline.evolve(m, U, rho, w.steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING,
-                               0, w.steps, w.checkpoint_every)
-    ev[1].record()
-    opts = tcm.make_opts(w.steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_LAB, 0, 1,
-                         w.checkpoint_every)
-    gg = torch.zeros(m.n, dtype=torch.float64, device="cuda")
-    gd = torch.zeros(m.n, dtype=torch.float64, device="cuda")
-    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    ws = torch.empty(tcm.tc_evolve_backward_workspace_size(m, opts), dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    ev[2].record()
-    tcm.tc_evolve_backward(m, H, U, opts, ck, loss, gg, gd, ws=ws)
-    ev[3].record()
-    torch.cuda.synchronize()
-    fwd = ev[0].elapsed_time(ev[1])
-    bwd = ev[2].elapsed_time(ev[3])
-    return {"workload": w.name, "N": inst.N, "steps": w.steps, "dtype": "f32",
-            "forward_s": fwd / 1000.0, "backward_s": bwd / 1000.0,
-            "backward_over_forward": bwd / fwd, "loss": float(loss.item())}
+    rho0 = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
+    out = {"workload": w.name, "N": inst.N, "steps": w.steps, "dtype": "f32"}
+    for key, sec in (("dense", False), ("sectors", True)):
+        rho = rho0.clone()
+        pipeline.evolve(m, U, rho.clone(), 4, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING,
+                        sectors=sec)                                         # warm-up
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        _, _, ck = pipeline.evolve(m, U, rho, w.steps, w.dt, tcm.TC_GEMM_F32,
+                                   tcm.TC_FRAME_ROTATING, 0, w.steps, w.checkpoint_every,
+                                   sectors=sec)
+        ev[1].record()
+        opts = tcm.make_opts(w.steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_LAB, 0, 1,
+                             w.checkpoint_every, sectors=int(sec))
+        gg = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+        gd = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ws = torch.empty(tcm.tc_evolve_backward_workspace_size(m, opts), dtype=torch.uint8,
+                         device="cuda")
+        torch.cuda.synchronize()
+        ev[2].record()
+        tcm.tc_evolve_backward(m, H, U, opts, ck, loss, gg, gd, ws=ws)
+        ev[3].record()
+        torch.cuda.synchronize()
+        fwd = ev[0].elapsed_time(ev[1])
+        bwd = ev[2].elapsed_time(ev[3])
+        out[key] = {"forward_s": fwd / 1000.0, "backward_s": bwd / 1000.0,
+                    "backward_over_forward": bwd / fwd, "loss": float(loss.item())}
+        del ck, ws
+    return out
 
 
 def bench_open11(tcm, pipeline, ti, steps=20):

@@ -255,7 +255,12 @@ int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype,
 int tc_evolve_backward_workspace_size(const tc_model* m, int64_t N,
                                       const tc_evolve_opts* o, size_t* bytes);
 
-/* Gradient of L = Tr(O rho(steps)), O = sum_i s_i^+ s_i^- (TC_OBS_EXCITED_TOTAL),
+/* With o->sectors = 1 the sweep runs by excitation sectors: O, U and every
+ * dH/dtheta conserve the excitation number, so L and its gradient depend on
+ * the diagonal blocks of rho only and the adjoint splits into one independent
+ * sweep per sector on d_k x d_k blocks (grouped products, G_k = L(A_k, M_k)
+ * per block); the checkpoints are the same full matrices.
+ * Gradient of L = Tr(O rho(steps)), O = sum_i s_i^+ s_i^- (TC_OBS_EXCITED_TOTAL),
  * with respect to g_i and delta_i (w_a,i = 1 + delta_i), for a run of tc_evolve
  * with the same model, U and opts (frame lab, no renormalisation) whose
  * checkpoints (device [steps/checkpoint_every + 1][N][N], rho_dtype) were

@@ -130,6 +130,37 @@ int launch_phase_minus_identity_c128(const c128* U, int64_t ldu, double ph_re, d
 int launch_phase_minus_identity_c64(const c128* U, int64_t ldu, double ph_re, double ph_im,
                                     c64* out, int64_t ldo, int64_t N, hipStream_t s);
 
+// ---- block-diagonal storage of padded sectors (sectors.hip)
+// Block k (k < nb) is dim[k] x dim[k], row-major, at element offset boff[k]
+// (boff[nb] = total elements); its rows are the padded sorted positions
+// spo[k] .. spo[k] + dim[k] - 1, and position p holds basis state perm[p]
+// (-1 for padding).  All arrays are device memory.
+struct BlockTable {
+  const int64_t* boff;
+  const int64_t* spo;
+  const int64_t* dim;
+  const int32_t* perm;
+  int nb;
+};
+// what = 0: identity blocks; 1: diag(sum_i s_i^+ s_i^-) over the block's states
+int launch_block_fill_c128(const BlockTable& t, int64_t total, int what, int n, c128* out,
+                           hipStream_t s);
+int launch_block_fill_c64(const BlockTable& t, int64_t total, int what, int n, c64* out,
+                          hipStream_t s);
+// out = -i scale (H_k - (w_c k + mu) I) for every block (0 at padding)
+int launch_block_minus_i_shift(const BlockTable& t, int64_t total, const double* H, int64_t ldh,
+                               double omega_c, double mu, double scale, c128* out, hipStream_t s);
+// full[s_i][s_j] = G_k[i][j] over the blocks' states
+int launch_block_scatter(const BlockTable& t, int64_t total, const c128* G, c128* full, int64_t ld,
+                         hipStream_t s);
+// diag[p] = diagonal element of position p (p < Np)
+int launch_block_diag_c128(const BlockTable& t, const c128* blocks, int64_t Np, c128* diag,
+                           hipStream_t s);
+int launch_block_diag_c64(const BlockTable& t, const c64* blocks, int64_t Np, c64* diag,
+                          hipStream_t s);
+int launch_scale_vec_c128(c128* x, int64_t count, double a, hipStream_t s);
+int launch_accumulate_vec_c64(const c64* t, c128* m, int64_t count, hipStream_t s);
+
 // bfloat16 hi/lo split of binary32 values.
 int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -182,7 +182,165 @@ int phase_minus_identity_impl(const c128* U, int64_t ldu, double ph_re, double p
   return TC_OK;
 }
 
+// ---- block-diagonal storage of padded sectors (the sector adjoint)
+// Block k is D_k x D_k (row-major, ld D_k) at element offset boff[k];
+// boff[nb] is the total.  Position p of the padded sorted order lies in the
+// block whose spo[k] <= p < spo[k] + D_k; perm[p] is its basis state or -1.
+__device__ __forceinline__ int block_of(const int64_t* __restrict__ off, int nb, int64_t e) {
+  int lo = 0, hi = nb - 1;               // last k with off[k] <= e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// what = 0: identity blocks; 1: diag(sum_i s_i^+ s_i^-) of the block's states
+template <typename E>
+__global__ void block_fill_kernel(BlockTable t, int what, int n, E* __restrict__ out) {
+  typedef typename real_of<E>::type T;
+  const int64_t total = t.boff[t.nb];
+  const uint64_t mask = (uint64_t(1) << n) - 1;
+  for (int64_t e = int64_t(blockIdx.x) * TPB + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * TPB) {
+    const int k = block_of(t.boff, t.nb, e);
+    const int64_t D = t.dim[k], r = e - t.boff[k], i = r / D, j = r % D;
+    double v = 0.0;
+    if (i == j) {
+      if (what == 0) {
+        v = 1.0;
+      } else {
+        const int32_t st = t.perm[t.spo[k] + i];
+        v = st >= 0 ? double(__popcll(uint64_t(st) & mask)) : 0.0;
+      }
+    }
+    out[e] = E{T(v), T(0)};
+  }
+}
+
+// out = -i scale (H_k - (w_c k + mu) I) on every block (0 at padding)
+__global__ void block_minus_i_shift_kernel(BlockTable t, const double* __restrict__ H, int64_t ldh,
+                                           double omega_c, double mu, double scale,
+                                           c128* __restrict__ out) {
+  const int64_t total = t.boff[t.nb];
+  for (int64_t e = int64_t(blockIdx.x) * TPB + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * TPB) {
+    const int k = block_of(t.boff, t.nb, e);
+    const int64_t D = t.dim[k], r = e - t.boff[k], i = r / D, j = r % D;
+    const int32_t si = t.perm[t.spo[k] + i], sj = t.perm[t.spo[k] + j];
+    double h = 0.0;
+    if (si >= 0 && sj >= 0) {
+      h = H[int64_t(si) * ldh + sj];
+      if (i == j) h -= omega_c * double(k) + mu;
+    }
+    out[e] = c128{0.0, -scale * h};
+  }
+}
+
+// full[s_i][s_j] = blocks (entries outside the blocks are left alone)
+__global__ void block_scatter_kernel(BlockTable t, const c128* __restrict__ G,
+                                     c128* __restrict__ full, int64_t ld) {
+  const int64_t total = t.boff[t.nb];
+  for (int64_t e = int64_t(blockIdx.x) * TPB + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * TPB) {
+    const int k = block_of(t.boff, t.nb, e);
+    const int64_t D = t.dim[k], r = e - t.boff[k], i = r / D, j = r % D;
+    const int32_t si = t.perm[t.spo[k] + i], sj = t.perm[t.spo[k] + j];
+    if (si >= 0 && sj >= 0) full[int64_t(si) * ld + sj] = G[e];
+  }
+}
+
+// diag[p] = the diagonal element of position p
+template <typename E>
+__global__ void block_diag_kernel(BlockTable t, const E* __restrict__ blocks, int64_t Np,
+                                  E* __restrict__ diag) {
+  for (int64_t p = int64_t(blockIdx.x) * TPB + threadIdx.x; p < Np;
+       p += int64_t(gridDim.x) * TPB) {
+    const int k = block_of(t.spo, t.nb, p);
+    const int64_t i = p - t.spo[k];
+    diag[p] = blocks[t.boff[k] + i * (t.dim[k] + 1)];
+  }
+}
+
+__global__ void scale_vec_kernel(c128* __restrict__ x, int64_t count, double a) {
+  for (int64_t e = int64_t(blockIdx.x) * TPB + threadIdx.x; e < count;
+       e += int64_t(gridDim.x) * TPB) {
+    x[e].re *= a;
+    x[e].im *= a;
+  }
+}
+
+__global__ void accumulate_vec_kernel(const c64* __restrict__ t, c128* __restrict__ m,
+                                      int64_t count) {
+  for (int64_t e = int64_t(blockIdx.x) * TPB + threadIdx.x; e < count;
+       e += int64_t(gridDim.x) * TPB) {
+    m[e].re += double(t[e].re);
+    m[e].im += double(t[e].im);
+  }
+}
+
+unsigned grid1(int64_t count) {
+  int64_t g = (count + TPB - 1) / TPB;
+  return unsigned(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
 }  // namespace
+
+int launch_block_fill_c128(const BlockTable& t, int64_t total, int what, int n, c128* out,
+                           hipStream_t s) {
+  if (total <= 0) return TC_OK;
+  hipLaunchKernelGGL(block_fill_kernel<c128>, dim3(grid1(total)), dim3(TPB), 0, s, t, what, n, out);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_block_fill_c64(const BlockTable& t, int64_t total, int what, int n, c64* out,
+                          hipStream_t s) {
+  if (total <= 0) return TC_OK;
+  hipLaunchKernelGGL(block_fill_kernel<c64>, dim3(grid1(total)), dim3(TPB), 0, s, t, what, n, out);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_block_minus_i_shift(const BlockTable& t, int64_t total, const double* H, int64_t ldh,
+                               double omega_c, double mu, double scale, c128* out, hipStream_t s) {
+  if (total <= 0) return TC_OK;
+  hipLaunchKernelGGL(block_minus_i_shift_kernel, dim3(grid1(total)), dim3(TPB), 0, s, t, H, ldh,
+                     omega_c, mu, scale, out);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_block_scatter(const BlockTable& t, int64_t total, const c128* G, c128* full, int64_t ld,
+                         hipStream_t s) {
+  if (total <= 0) return TC_OK;
+  hipLaunchKernelGGL(block_scatter_kernel, dim3(grid1(total)), dim3(TPB), 0, s, t, G, full, ld);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_block_diag_c128(const BlockTable& t, const c128* blocks, int64_t Np, c128* diag,
+                           hipStream_t s) {
+  if (Np <= 0) return TC_OK;
+  hipLaunchKernelGGL(block_diag_kernel<c128>, dim3(grid1(Np)), dim3(TPB), 0, s, t, blocks, Np, diag);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_block_diag_c64(const BlockTable& t, const c64* blocks, int64_t Np, c64* diag,
+                          hipStream_t s) {
+  if (Np <= 0) return TC_OK;
+  hipLaunchKernelGGL(block_diag_kernel<c64>, dim3(grid1(Np)), dim3(TPB), 0, s, t, blocks, Np, diag);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_scale_vec_c128(c128* x, int64_t count, double a, hipStream_t s) {
+  if (count <= 0) return TC_OK;
+  hipLaunchKernelGGL(scale_vec_kernel, dim3(grid1(count)), dim3(TPB), 0, s, x, count, a);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
+int launch_accumulate_vec_c64(const c64* t, c128* m, int64_t count, hipStream_t s) {
+  if (count <= 0) return TC_OK;
+  hipLaunchKernelGGL(accumulate_vec_kernel, dim3(grid1(count)), dim3(TPB), 0, s, t, m, count);
+  TC_TRY_HIP(hipGetLastError());
+  return TC_OK;
+}
 
 int launch_ham_sector(const ModelArgs& m, int k, int64_t d, double* H, int64_t ldh,
                       hipStream_t s) {

@@ -24,15 +24,16 @@ def setup_module(module):
     tcm.lib()
 
 
-def gpu_grad(inst, dt, steps, every, mode, rho_dtype):
+def gpu_grad(inst, dt, steps, every, mode, rho_dtype, sectors=False):
     m = pipeline.model_of(inst)
     H, U = pipeline.propagator(m, dt)
     rdt = tcm.TC_C128 if rho_dtype == torch.complex128 else tcm.TC_C64
     rho = torch.from_numpy(inst.rho0()).to("cuda").to(rho_dtype)
     # the forward runs in the rotating frame (its checkpoints are lab-frame states)
     _, _, ck = pipeline.evolve(m, U, rho, steps, dt, mode, tcm.TC_FRAME_ROTATING, 0,
-                               steps if steps else 1, every)
-    opts = tcm.make_opts(steps, dt, mode, rdt, tcm.TC_FRAME_LAB, 0, 1, every)
+                               steps if steps else 1, every, sectors=sectors)
+    opts = tcm.make_opts(steps, dt, mode, rdt, tcm.TC_FRAME_LAB, 0, 1, every,
+                         sectors=int(sectors))
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     gg = torch.zeros(inst.n, dtype=torch.float64, device="cuda")
     gd = torch.zeros(inst.n, dtype=torch.float64, device="cuda")
@@ -41,11 +42,16 @@ def gpu_grad(inst, dt, steps, every, mode, rho_dtype):
     return float(loss.item()), gg.cpu().numpy(), gd.cpu().numpy()
 
 
+@pytest.mark.parametrize("sectors", [False, True])
 @pytest.mark.parametrize("state,steps,every", [("gaussian", 40, 7), ("excited", 40, 40), ("haar2", 13, 5)])
-def test_adjoint_fp64_small(state, steps, every):
+def test_adjoint_fp64_small(state, steps, every, sectors):
+    """N = 32, FP64: loss to 1e-12 and gradients to 1e-9 of the oracle's
+    Daleckii-Krein gradient, with dense products and by excitation sectors
+    (one independent sweep per diagonal block; a short last segment for
+    steps = 40, every = 7 and 13, 5)."""
     inst = ti.random_model(3, 3, 61, delta_sigma=0.01, state=state)
     dt = 0.5
-    L, gg, gd = gpu_grad(inst, dt, steps, every, tcm.TC_GEMM_F64, torch.complex128)
+    L, gg, gd = gpu_grad(inst, dt, steps, every, tcm.TC_GEMM_F64, torch.complex128, sectors)
     Lo, go, do = ograd.grad_daleckii_krein(inst.n, inst.c, inst.g, inst.omega_a - 1, inst.rho0(),
                                            steps * dt)
     scale = max(np.max(np.abs(go)), np.max(np.abs(do)))
@@ -54,9 +60,10 @@ def test_adjoint_fp64_small(state, steps, every):
     assert np.max(np.abs(gd - do)) <= 1e-9 * scale
 
 
-def test_adjoint_zero_steps():
+@pytest.mark.parametrize("sectors", [False, True])
+def test_adjoint_zero_steps(sectors):
     inst = ti.random_model(2, 2, 62, state="gaussian")
-    L, gg, gd = gpu_grad(inst, 0.3, 0, 1, tcm.TC_GEMM_F64, torch.complex128)
+    L, gg, gd = gpu_grad(inst, 0.3, 0, 1, tcm.TC_GEMM_F64, torch.complex128, sectors)
     assert np.all(gg == 0) and np.all(gd == 0)
     assert abs(L - oobs.excitation_total(inst.rho0(), inst.n, inst.c)) < 1e-14
 
@@ -83,35 +90,38 @@ def grad8_oracle():
     return w, inst, Lo, go, do, fg, fd
 
 
+@pytest.mark.parametrize("sectors", [False, True])
 @pytest.mark.parametrize("mode,dtype,tol", [
     (tcm.TC_GEMM_F32, torch.complex64, 1e-4),
     (tcm.TC_GEMM_F64, torch.complex128, 1e-9),
 ])
-def test_adjoint_grad8_workload(grad8_oracle, mode, dtype, tol):
+def test_adjoint_grad8_workload(grad8_oracle, mode, dtype, tol, sectors):
     """n=8, c=8 (N=2304), dt=0.05 x 500, checkpoints every 50: complex64 forward and
     FP32 sweep within 1e-4 of max|grad| (FP64 run within 1e-9) of the oracle's
     Daleckii-Krein gradient; finite differences agree with both."""
     w, inst, Lo, go, do, fg, fd = grad8_oracle
     t0 = time.time()
-    L, gg, gd = gpu_grad(inst, w.dt, w.steps, w.checkpoint_every, mode, dtype)
-    print(f"gpu forward + adjoint mode={mode}: {time.time() - t0:.2f}s", flush=True)
+    L, gg, gd = gpu_grad(inst, w.dt, w.steps, w.checkpoint_every, mode, dtype, sectors)
+    print(f"gpu forward + adjoint mode={mode} sectors={sectors}: {time.time() - t0:.2f}s",
+          flush=True)
     scale = max(np.max(np.abs(go)), np.max(np.abs(do)))
     eg = np.max(np.abs(gg - go)) / scale
     ed = np.max(np.abs(gd - do)) / scale
-    print(f"grad8 mode={mode}: loss {L:.12f} (oracle {Lo:.12f}), rel err g {eg:.2e}, delta {ed:.2e}",
-          flush=True)
+    print(f"grad8 mode={mode} sectors={sectors}: loss {L:.12f} (oracle {Lo:.12f}), rel err g "
+          f"{eg:.2e}, delta {ed:.2e}", flush=True)
     assert abs(L - Lo) <= max(tol, 1e-12) * max(1.0, abs(Lo))
     assert eg <= tol and ed <= tol
     # the FD reference agrees with the oracle gradient to FD accuracy
     assert np.max(np.abs(fg - go)) <= 1e-5 * scale and np.max(np.abs(fd - do)) <= 1e-5 * scale
 
 
-def test_autograd_function():
+@pytest.mark.parametrize("sectors", [False, True])
+def test_autograd_function(sectors):
     inst = ti.random_model(3, 2, 63, delta_sigma=0.01, state="gaussian")
     g = torch.tensor(inst.g, dtype=torch.float64, requires_grad=True)
     d = torch.tensor(inst.omega_a - 1, dtype=torch.float64, requires_grad=True)
     rho0 = torch.from_numpy(inst.rho0()).to("cuda")
-    loss = TCMLoss.apply(g, d, inst.n, inst.c, rho0, 0.4, 30, 10, tcm.TC_GEMM_F64)
+    loss = TCMLoss.apply(g, d, inst.n, inst.c, rho0, 0.4, 30, 10, tcm.TC_GEMM_F64, sectors)
     (2.5 * loss).backward()
     Lo, go, do = ograd.grad_daleckii_krein(inst.n, inst.c, inst.g, inst.omega_a - 1, inst.rho0(), 12.0)
     assert abs(float(loss.detach()) - Lo) < 1e-12
