@@ -139,10 +139,11 @@ def bench_batch64(tcm, pipeline, ti, steps=50):
     tune_s = time.perf_counter() - t0
     rho0 = [torch.from_numpy(i.rho0()).to("cuda").to(torch.complex64) for i in w.instances]
 
-    def run(k):
+    def run(k, mode=tcm.TC_GEMM_F32, sectors=0):
         rhos = [r.clone() for r in rho0]
         pops = [torch.zeros(k + 1, dtype=torch.float64, device="cuda") for _ in models]
-        opts = tcm.make_opts(k, w.dt, tcm.TC_GEMM_F32, tcm.TC_C64, tcm.TC_FRAME_ROTATING, 0, 1, 0, 1)
+        opts = tcm.make_opts(k, w.dt, mode, tcm.TC_C64, tcm.TC_FRAME_ROTATING, 0, 1, 0, 1,
+                             sectors=sectors)
         insts = [tcm.make_instance(m, U, r, p) for m, U, r, p in zip(models, Us, rhos, pops)]
         ws = torch.empty(tcm.tc_evolve_workspace_size(insts, opts), dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
@@ -156,12 +157,22 @@ def bench_batch64(tcm, pipeline, ti, steps=50):
     run(16)                                                      # warm-up
     ms = run(steps)
     flop = 16.0 * sum(float(m.N) ** 3 for m in models) * steps
-    return {"workload": w.name, "instances": len(models), "N_min": min(m.N for m in models),
-            "N_max": maxN, "dtype": "f32", "steps": steps, "steps_per_s": steps / (ms * 1e-3),
-            "ms_per_step": ms / steps, "tflops": flop / (ms * 1e-3) / 1e12,
-            "autotune_s": tune_s,
-            "tile_variants": {str(b): tcm.tc_autotune_query(tcm.TC_GEMM_F32, b)
-                              for b in (256, 1024, 4096, 7168)}}
+    out = {"workload": w.name, "instances": len(models), "N_min": min(m.N for m in models),
+           "N_max": maxN, "dtype": "f32", "steps": steps, "steps_per_s": steps / (ms * 1e-3),
+           "ms_per_step": ms / steps, "tflops": flop / (ms * 1e-3) / 1e12,
+           "autotune_s": tune_s,
+           "tile_variants": {str(b): tcm.tc_autotune_query(tcm.TC_GEMM_F32, b)
+                             for b in (256, 1024, 4096, 7168)}}
+    # the same batch by excitation-sector blocks (all instances' blocks in one
+    # grouped launch per product), complex FP32 and split-BF16
+    for key, mode in (("sectors_fp32", tcm.TC_GEMM_F32), ("sectors_split", tcm.TC_GEMM_SPLIT_BF16)):
+        run(8, mode, 1)
+        ms = run(steps, mode, 1)
+        sflop = sum(sector_flop_per_step(m.n, m.c) for m in models) * steps
+        out[key] = {"steps_per_s": steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                    "tflops": sflop / (ms * 1e-3) / 1e12,
+                    "dense_equivalent_tflops": flop / (ms * 1e-3) / 1e12}
+    return out
 
 
 def bench_grad8(tcm, pipeline, ti):

@@ -324,7 +324,9 @@ __global__ void grouped_readout_kernel(const ReadoutItem* __restrict__ items,
   for (int mm = 0; mm <= it.c; ++mm) {
     double part = 0.0, ex = 0.0;
     for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
-      const double d = double(rho[s * it.ld + s].re);
+      const int64_t q = it.map ? int64_t(it.map[s]) : s;
+      if (q < 0) continue;
+      const double d = double(rho[q * it.ld + q].re);
       part += d;
       ex += double(popc64(uint64_t(s) & mask)) * d;
     }

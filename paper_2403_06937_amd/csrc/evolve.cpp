@@ -52,6 +52,10 @@ struct InstPlan {
   std::vector<Planes4> sopA, sopB;
   Planes4 sXp, sRt;
   SplitGrouped sg1, sg2;
+  // the block products of one step, largest blocks first (kept so that a
+  // batch of instances can launch all of theirs together)
+  std::vector<GemmDesc> sd1, sd2;
+  std::vector<SplitProduct> ssd1, ssd2;
 };
 
 int validate_opts(const tc_evolve_opts* o) {
@@ -338,7 +342,7 @@ int copy_checkpoint(const InstPlan& p, const tc_instance& in, const tc_evolve_op
 //   rho'_{:k,k} = X_{:k,k} U_k^dag (rotating: + X_{:k,k}), planes of rho'^T written
 // with K offsets at sector starts (multiples of 128).
 int prepare_sector_split(InstPlan& p, const tc_evolve_opts& o, const std::vector<int>& order,
-                         hipStream_t s) {
+                         bool build, hipStream_t s) {
   const int64_t Np = p.Np;
   const bool rot = o.frame == TC_FRAME_ROTATING;
   c64* rho = static_cast<c64*>(p.rho);
@@ -351,7 +355,9 @@ int prepare_sector_split(InstPlan& p, const tc_evolve_opts& o, const std::vector
   }
   TC_TRY_HIP(hipMemsetAsync(p.sXp.base, 0, size_t(4) * p.sXp.rows * p.sXp.ld * 2, s));
   TC_RETURN_IF(split_matrix(rho, p.ldr, Np, Np, true, false, p.sRt, s));
-  std::vector<SplitProduct> d1, d2;
+  std::vector<SplitProduct>& d1 = p.ssd1;
+  std::vector<SplitProduct>& d2 = p.ssd2;
+  d1.clear(); d2.clear();
   for (int k : order) {
     const int64_t off = p.spo[k], d = p.spd[k];
     SplitProduct g1;                    // X_{k, k:} = op_k rho_{k, k:}
@@ -371,13 +377,17 @@ int prepare_sector_split(InstPlan& p, const tc_evolve_opts& o, const std::vector
     d1.push_back(g1);
     d2.push_back(g2);
   }
+  if (!build) return TC_OK;
   const int ns = int(p.spd.size());
   TC_RETURN_IF(split_grouped_build(d1, p.items, &p.sg1, s));
   TC_RETURN_IF(split_grouped_build(d2, p.items + split_grouped_bytes(ns), &p.sg2, s));
   return TC_OK;
 }
 
-int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+// build: also upload the grouped products of the instance's own step (false
+// when a batch launches the blocks of all its instances together).
+int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s,
+                    bool build = true) {
   TC_TRY_HIP(hipMemsetAsync(p.scratch, 0, 4 * sizeof(double), s));
   const int64_t N = p.N, Np = p.Np;
   const int n = p.m.n;
@@ -423,11 +433,13 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
   for (int k = 0; k < ns; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return p.spd[a] > p.spd[b]; });
-  if (o.gemm_mode == TC_GEMM_SPLIT_BF16) return prepare_sector_split(p, o, order, s);
+  if (o.gemm_mode == TC_GEMM_SPLIT_BF16) return prepare_sector_split(p, o, order, build, s);
   auto at = [&](void* base, int64_t r, int64_t c, int64_t ld) {
     return static_cast<void*>(static_cast<char*>(base) + (size_t(r) * size_t(ld) + size_t(c)) * eb);
   };
-  std::vector<GemmDesc> d1, d2;
+  std::vector<GemmDesc>& d1 = p.sd1;
+  std::vector<GemmDesc>& d2 = p.sd2;
+  d1.clear(); d2.clear();
   for (int k : order) {
     const int64_t off = p.spo[k], d = p.spd[k];
     const void* blk = static_cast<char*>(p.blocks) + p.boff[k] * eb;
@@ -446,6 +458,7 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
     d1.push_back(g1);
     d2.push_back(g2);
   }
+  if (!build) return TC_OK;
   const int v = tile_variant_for(N, f64);
   TC_RETURN_IF(grouped_build(d1, f64, v, p.items, &p.g1, s));
   TC_RETURN_IF(grouped_build(d2, f64, v, p.items + grouped_bytes(ns), &p.g2, s));
@@ -585,11 +598,15 @@ struct BatchBufs {
 };
 
 bool use_batched(int count, const tc_evolve_opts& o) {
-  return count > 1 && o.gemm_mode != TC_GEMM_SPLIT_BF16 && !o.sectors;
+  return count > 1 && (o.gemm_mode != TC_GEMM_SPLIT_BF16 || o.sectors);
 }
 
-void plan_batch(Arena& ar, int count, BatchBufs* b) {
-  b->items = static_cast<char*>(ar.take(8 * grouped_bytes(count)));
+// sector_items: total sector blocks of the batch (0 without sectors); the
+// block products of all instances share two groups per tile shape
+void plan_batch(Arena& ar, int count, int64_t sector_items, BatchBufs* b) {
+  const size_t blocks = std::max(grouped_bytes(int(sector_items)),
+                                 split_grouped_bytes(int(sector_items)));
+  b->items = static_cast<char*>(ar.take(std::max(8 * grouped_bytes(count), 4 * blocks)));
   b->ritems = static_cast<ReadoutItem*>(ar.take(size_t(count) * sizeof(ReadoutItem)));
   b->counter = static_cast<int*>(ar.take(sizeof(int)));
 }
@@ -611,34 +628,75 @@ void step_descs(const InstPlan& p, const tc_evolve_opts& o, GemmDesc& g1, GemmDe
   g2.herm = o.full_product == 0;
 }
 
+// Sector blocks of all instances of a batch (0 without sectors).
+int64_t sector_items(const tc_instance* inst, int count, const tc_evolve_opts& o) {
+  if (!o.sectors) return 0;
+  int64_t t = 0;
+  for (int b = 0; b < count; ++b)
+    t += inst[b].model->n_atoms + inst[b].model->photon_cutoff + 1;
+  return t;
+}
+
 int64_t gcd64(int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; }
 
 int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int count,
                    const tc_evolve_opts& o, const BatchBufs& bb, hipStream_t s) {
   const bool f64 = o.gemm_mode == TC_GEMM_F64;
-  for (int b = 0; b < count; ++b) TC_RETURN_IF(prepare(plans[b], inst[b], o, s));
+  const bool sec = o.sectors != 0, split = o.gemm_mode == TC_GEMM_SPLIT_BF16;
+  for (int b = 0; b < count; ++b)
+    TC_RETURN_IF(sec ? prepare_sectors(plans[b], inst[b], o, s, false)
+                     : prepare(plans[b], inst[b], o, s));
   // group the products by tile shape (autotuner table per dimension bucket)
   // and by whether N is a multiple of the tile: those run one workgroup per
-  // tile with the unchecked tile (fewer registers), the rest persistently
+  // tile with the unchecked tile (fewer registers), the rest persistently.
+  // By sectors, the block products of every instance (whole tiles of the
+  // instance's padding) go into one group per tile shape, largest K first.
   std::vector<GemmDesc> d1[3][2], d2[3][2];
+  std::vector<SplitProduct> sp1, sp2;
   for (int b = 0; b < count; ++b) {
-    GemmDesc g1, g2;
-    step_descs(plans[b], o, g1, g2);
     const int v = tile_variant_for(plans[b].N, f64);
-    const int edge = v == 1 ? 128 : 64;
-    const int e = plans[b].N % edge == 0 ? 0 : 1;
-    d1[v][e].push_back(g1);
-    d2[v][e].push_back(g2);
+    if (sec && split) {
+      sp1.insert(sp1.end(), plans[b].ssd1.begin(), plans[b].ssd1.end());
+      sp2.insert(sp2.end(), plans[b].ssd2.begin(), plans[b].ssd2.end());
+    } else if (sec) {
+      d1[v][0].insert(d1[v][0].end(), plans[b].sd1.begin(), plans[b].sd1.end());
+      d2[v][0].insert(d2[v][0].end(), plans[b].sd2.begin(), plans[b].sd2.end());
+    } else {
+      GemmDesc g1, g2;
+      step_descs(plans[b], o, g1, g2);
+      const int edge = v == 1 ? 128 : 64;
+      const int e = plans[b].N % edge == 0 ? 0 : 1;
+      d1[v][e].push_back(g1);
+      d2[v][e].push_back(g2);
+    }
   }
+  auto by_k = [](const auto& x, const auto& y) { return x.K > y.K; };
+  auto by_kp = [](const SplitProduct& x, const SplitProduct& y) { return x.Kp > y.Kp; };
+  std::stable_sort(sp1.begin(), sp1.end(), by_kp);
+  std::stable_sort(sp2.begin(), sp2.end(), by_kp);
   GroupedProducts G1[3][2], G2[3][2];
+  SplitGrouped S1, S2;
   char* it = bb.items;
+  const size_t gstep = sec ? std::max(grouped_bytes(int(d1[1][0].size() + d1[2][0].size())),
+                                      split_grouped_bytes(int(sp1.size())))
+                           : grouped_bytes(count);
+  if (sec && split) {
+    TC_RETURN_IF(split_grouped_build(sp1, it, &S1, s));
+    it += gstep;
+    TC_RETURN_IF(split_grouped_build(sp2, it, &S2, s));
+    it += gstep;
+  }
   for (int v = 1; v <= 2; ++v)
     for (int e = 0; e < 2; ++e) {
       if (d1[v][e].empty()) continue;
+      if (sec) {
+        std::stable_sort(d1[v][e].begin(), d1[v][e].end(), by_k);
+        std::stable_sort(d2[v][e].begin(), d2[v][e].end(), by_k);
+      }
       TC_RETURN_IF(grouped_build(d1[v][e], f64, v, it, &G1[v][e], s));
-      it += grouped_bytes(count);
+      it += gstep;
       TC_RETURN_IF(grouped_build(d2[v][e], f64, v, it, &G2[v][e], s));
-      it += grouped_bytes(count);
+      it += gstep;
       G1[v][e].persistent = G2[v][e].persistent = e == 1;
     }
   bool rec = false, ckpt = false;
@@ -650,6 +708,7 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
     ri[b].c = plans[b].m.c;
     ri[b].pop = inst[b].pop_out;
     ri[b].pdist = inst[b].photon_dist_out;
+    ri[b].map = sec ? plans[b].inv : nullptr;
     rec = rec || inst[b].pop_out || inst[b].photon_dist_out;
     ckpt = ckpt || inst[b].checkpoints;
   }
@@ -666,8 +725,10 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
     if (inst[b].checkpoints) TC_RETURN_IF(copy_checkpoint(plans[b], inst[b], o, 0, 0.0, s));
 
   auto one_step = [&](int64_t st, hipStream_t q) -> int {
+    TC_RETURN_IF(split_grouped_run(S1, q));
     for (int v = 1; v <= 2; ++v)
       for (int e = 0; e < 2; ++e) TC_RETURN_IF(grouped_run(G1[v][e], q));
+    TC_RETURN_IF(split_grouped_run(S2, q));
     for (int v = 1; v <= 2; ++v)
       for (int e = 0; e < 2; ++e) TC_RETURN_IF(grouped_run(G2[v][e], q));
     for (int b = 0; b < count; ++b) TC_RETURN_IF(dissipate(plans[b], o, q));
@@ -756,7 +817,7 @@ int tc_evolve_workspace_size(const tc_instance* inst, int32_t count, const tc_ev
   }
   if (use_batched(count, *o)) {
     BatchBufs bb;
-    plan_batch(ar, count, &bb);
+    plan_batch(ar, count, sector_items(inst, count, *o), &bb);
   }
   *bytes = ar.used;
   return TC_OK;
@@ -782,7 +843,7 @@ int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o, v
   }
   if (use_batched(count, *o)) {
     BatchBufs bb;
-    plan_batch(ar, count, &bb);
+    plan_batch(ar, count, sector_items(inst, count, *o), &bb);
     TC_RETURN_IF(evolve_batched(plans, inst, count, *o, bb, s));
   } else {
     for (int b = 0; b < count; ++b) TC_RETURN_IF(evolve_one(plans[b], inst[b], *o, s));

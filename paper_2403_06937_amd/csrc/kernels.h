@@ -59,6 +59,7 @@ struct ReadoutItem {
   int n, c;
   double* pop;      // may be NULL
   double* pdist;    // may be NULL
+  const int32_t* map;   // NULL, or the position of each basis state in rho (sector order)
 };
 int launch_grouped_readout(const ReadoutItem* items_dev, int count, bool c128_storage,
                            const int* counter, hipStream_t s);
