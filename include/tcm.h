@@ -188,7 +188,9 @@ typedef struct {
                                triangle is multiplied and mirrored (rho(0) must be
                                Hermitian); 1: every tile of both products        */
   int32_t sectors;          /* 0: dense N x N products.  1: excitation-sector
-                               block stepping (TC_GEMM_F64 / TC_GEMM_F32 only):
+                               block stepping, in every gemm_mode (count > 1:
+                               the blocks of all instances in one grouped
+                               launch per product):
                                H of Eq. (4) conserves k = m + |l|, so in the
                                basis sorted by k (stable within a sector) U is
                                block diagonal, U = diag(U_0 .. U_{n+c}), and
