@@ -171,3 +171,42 @@ def test_paper_model_n10_split_bf16():
     perr = abs(float(pop[-1].item()) - float(np.sum(exc * np.abs(psiT) ** 2)))
     print(f"paper model n=10 split-bf16: max-entry {err:.2e}, population {perr:.2e}")
     assert err < 1e-5 and perr < 1e-5
+
+
+@pytest.mark.parametrize("mode,frame,dtype,steps,tol", [
+    (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 40, 1e-10),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 200, 1e-5)])
+def test_paper_model_equal_g_large(mode, frame, dtype, steps, tol):
+    """The paper's model at n = 13 (N = 8192), equal couplings at resonance,
+    all atoms excited: the state stays in the symmetric states |m>|D_{n-m}>,
+    whose (n + 1)-state chain (couplings g (m + 1) sqrt(n - m)) is solved
+    exactly: every record of the photon-number distribution and of the atomic
+    population against it, and the final trace.  U from the shifted, scaled
+    exponential."""
+    n, g = 13, 0.02
+    m = tcm.Model(n, n, [g] * n, [1.0] * n)
+    dt = 0.05
+    _, U = pipeline.sector_propagator(m, n, dt)
+    D = 1 << n
+    rho = torch.zeros((D, D), dtype=dtype, device="cuda")
+    rho[0, 0] = 1.0                           # all excited: first sector position
+    pop, pd, _ = pipeline.evolve_sector(m, n, U, rho, steps, dt, mode, frame, 20,
+                                        record_photons=True)
+    chain = np.diag([float(n)] * (n + 1))
+    for mm in range(n):
+        chain[mm, mm + 1] = chain[mm + 1, mm] = g * (mm + 1) * np.sqrt(n - mm)
+    lam, V = np.linalg.eigh(chain)
+    pdn = pd.cpu().numpy()
+    popn = pop.cpu().numpy()
+    err = 0.0
+    for s in range(steps + 1):
+        c = V @ (np.exp(-1j * lam * s * dt) * V[0].conj())        # chain amplitudes, start m = 0
+        p = np.abs(c) ** 2                                        # P(m photons)
+        err = max(err, float(np.max(np.abs(pdn[s] - p))))
+        # sum_i <s_i^+ s_i^-> = n - <a^dag a>
+        err = max(err, abs(popn[s] - (n - float(np.sum(np.arange(n + 1) * p)))))
+    r = rho.cpu().numpy().astype(np.complex128)
+    tr = np.trace(r)
+    print(f"paper model n=13 equal g mode={mode}: max record error {err:.2e}, trace {tr:.12f}")
+    assert err < tol
+    assert abs(tr - 1.0) < tol
