@@ -16,12 +16,16 @@
 //
 // Tiling: 128 x 128 outputs per workgroup, K tile 32, all eight planes
 // double-buffered in LDS (128 KB).  Default shape: 512 threads = 2 x 4 waves
-// of 64 x 32 outputs (4 x 2 blocks), two waves per SIMD, the next K tile
-// staged in registers and written to LDS at the start of the iteration after
-// its load, so that the load has a whole iteration to arrive.  Measured at
-// N = 12288 (mean of a full and a triangle launch): 21.2 ms; with the planes
-// stored one after another instead of interleaved 24.8 ms, with the store at
-// the end of the loading iteration 25.2 ms; 4 waves of 64 x 64: 29.5 ms.
+// of 64 x 32 outputs (4 x 2 blocks), two waves per SIMD, run as two ping-pong
+// groups: while one wave of a SIMD issues the products of a K tile from
+// fragments it already holds, the other reads its fragments, stores its share
+// of the next tile (staged in registers) and loads the one after, with two
+// workgroup barriers per K tile.  Measured at N = 12288 (mean of a full and a
+// triangle launch, one box): 18.6 ms, against 20.4 ms with both waves of a
+// SIMD in lockstep (reads, then products, one barrier per K tile).  Earlier
+// lockstep measurements: the planes stored one after another instead of
+// interleaved 24.8 ms against 21.2 ms, the store at the end of the loading
+// iteration 25.2 ms; 4 waves of 64 x 64: 29.5 ms.
 // A variant with one wave per SIMD (128 x 32 outputs each, accumulators in
 // AGPRs) that reads its B fragments straight from global memory ran at 31 ms.
 // 16-byte chunks are XOR-swizzled by row and the planes padded so that
@@ -237,10 +241,19 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
 
 // Publishes this wave's LDS writes to the workgroup: waits for them, then a
 // barrier.  Outstanding global loads are not waited for (__syncthreads would
-// wait for those too); the memory clobber keeps the compiler from moving LDS
-// accesses across it.
+// wait for those too).  The wait and the barrier are builtins, not inline
+// asm, so that the compiler's wait-count tracking sees the LDS counter
+// drained here and later waits can be partial; the empty asm statements with
+// a memory clobber keep LDS accesses from moving across, and the scheduling
+// fences keep the machine scheduler from doing so.
+constexpr unsigned WAIT_LGKM0 = 0xC07F;   // s_waitcnt vmcnt(63) expcnt(7) lgkmcnt(0)
 __device__ __forceinline__ void sync_lds() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::: "memory");
 }
 
 // WGM x WGN waves, each owning WM x WN blocks of 16 x 16 outputs of a
@@ -253,7 +266,7 @@ __device__ __forceinline__ void sync_lds() {
 typedef u4 SplitLds[2][4][LDS_PLANE];
 #define LDS_AT(buf, q, row, chunk) [buf][q][(row) * 4 + (chunk)]
 
-template <int WGM, int WGN, int WM, int WN>
+template <int WGM, int WGN, int WM, int WN, bool PP>
 __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn, SplitLds& sA,
                                            SplitLds& sB) {
   constexpr int NT = 64 * WGM * WGN;
@@ -314,63 +327,143 @@ __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn,
   const int64_t ktiles = p.Kp / SPLIT_BK;
   const int lr = lane & 15, lc = lane >> 4;
   const u4 sgn = u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-  auto compute = [&](int buf) {
-    u4 b[WN][4];
+  u4 st[2 * RPT];
+  auto read_a = [&](u4 (&a)[4], int buf, int i) {
+    const int row = (wm * WM + i) * 16 + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = sA LDS_AT(buf, q, row, lc ^ swz(row));
+  };
+  auto read_b = [&](u4 (&b)[WN][4], int buf) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
       const int row = (wn * WN + j) * 16 + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) b[j][q] = sB LDS_AT(buf, q, row, lc ^ swz(row));
     }
+  };
+  // the twelve products of block row i with every block column of the wave
+  auto mma_row = [&](const u4 (&a)[4], const u4 (&b)[WN][4], int i) {
+    const u4 nih = a[PL_IH] ^ sgn, nil = a[PL_IL] ^ sgn;
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      const int row = (wm * WM + i) * 16 + lr;
-      u4 a[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = sA LDS_AT(buf, q, row, lc ^ swz(row));
-      const u4 nih = a[PL_IH] ^ sgn, nil = a[PL_IL] ^ sgn;
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        f4 re = acc_re[i][j], im = acc_im[i][j];
-        re = mma(a[PL_RH], b[j][PL_RH], re);
-        re = mma(a[PL_RH], b[j][PL_RL], re);
-        re = mma(a[PL_RL], b[j][PL_RH], re);
-        re = mma(nih, b[j][PL_IH], re);
-        re = mma(nih, b[j][PL_IL], re);
-        re = mma(nil, b[j][PL_IH], re);
-        im = mma(a[PL_RH], b[j][PL_IH], im);
-        im = mma(a[PL_RH], b[j][PL_IL], im);
-        im = mma(a[PL_RL], b[j][PL_IH], im);
-        im = mma(a[PL_IH], b[j][PL_RH], im);
-        im = mma(a[PL_IH], b[j][PL_RL], im);
-        im = mma(a[PL_IL], b[j][PL_RH], im);
-        acc_re[i][j] = re;
-        acc_im[i][j] = im;
-      }
+    for (int j = 0; j < WN; ++j) {
+      f4 re = acc_re[i][j], im = acc_im[i][j];
+      re = mma(a[PL_RH], b[j][PL_RH], re);
+      im = mma(a[PL_RH], b[j][PL_IH], im);
+      re = mma(a[PL_RH], b[j][PL_RL], re);
+      im = mma(a[PL_RH], b[j][PL_IL], im);
+      re = mma(a[PL_RL], b[j][PL_RH], re);
+      im = mma(a[PL_RL], b[j][PL_IH], im);
+      re = mma(nih, b[j][PL_IH], re);
+      im = mma(a[PL_IH], b[j][PL_RH], im);
+      re = mma(nih, b[j][PL_IL], re);
+      im = mma(a[PL_IH], b[j][PL_RL], im);
+      re = mma(nil, b[j][PL_IH], re);
+      im = mma(a[PL_IL], b[j][PL_RH], im);
+      acc_re[i][j] = re;
+      acc_im[i][j] = im;
     }
   };
 
-  // LDS buffer t % 2 holds tile t
-  u4 st[2 * RPT];
-  if (ktiles > 0) {
-    load(st, 0);
-    store(st, 0);
-    if (ktiles > 1) load(st, 1);
-  }
-  sync_lds();
-  for (int64_t kt = 0; kt < ktiles; ++kt) {
-    if (kt + 1 < ktiles) store(st, int((kt + 1) & 1));
-    if (kt + 2 < ktiles) load(st, kt + 2);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(int(kt & 1));
+  if constexpr (PP) {
+    // Ping-pong: waves w and w + 4 share a SIMD, so the workgroup splits into
+    // two groups of four, one wave of each on every SIMD.  A group alternates
+    // a memory phase (the fragments of K tile x from LDS into registers, its
+    // share of tile x + 1 from registers into LDS, its share of tile x + 2
+    // from global memory into registers) with a compute phase (the products of
+    // tile x from the registers, no memory access), and the second group runs
+    // one phase behind the first, separated by workgroup barriers: while one
+    // wave of a SIMD issues products back to back, the other moves data.
+    //
+    // Barriers: both groups pass the prologue barrier, then group 0 runs
+    // M(0) | C(0) | M(1) | ... | C(K-1) with a barrier after every phase, and
+    // group 1 passes one extra barrier first and none after its last C(K-1),
+    // so both pass 2K + 1 barriers.  Tile x + 1 overwrites the buffer of tile
+    // x - 1, whose last reader (group 1, M(x-1)) finished two barriers before
+    // group 0's M(x) and one before group 1's M(x); tile x is complete in LDS
+    // one barrier before its first reader.
+    static_assert(WGM * WGN == 8 && WGN == 4, "two groups of four waves");
+    const int grp = __builtin_amdgcn_readfirstlane(wave) >> 2;   // wave-uniform
+    u4 fa[WM][4], fb[WN][4];
+    auto memory = [&](int64_t x) {
+      const int buf = int(x & 1);
+      read_b(fb, buf);
+#pragma unroll
+      for (int i = 0; i < WM; ++i) read_a(fa[i], buf, i);
+      if (x + 1 < ktiles) store(st, int((x + 1) & 1));
+      if (x + 2 < ktiles) load(st, x + 2);
+    };
+    if (ktiles > 0) {
+      load(st, 0);
+      store(st, 0);
+      if (ktiles > 1) load(st, 1);
+    }
     sync_lds();
+    if (ktiles > 0 && grp == 1) sync_lds();
+    for (int64_t x = 0; x < ktiles; ++x) {
+      memory(x);
+      sync_lds();
+#pragma unroll
+      for (int i = 0; i < WM; ++i) mma_row(fa[i], fb, i);
+      if (grp == 0 || x + 1 < ktiles) sync_lds();
+    }
+  } else {
+    // One K tile from LDS buffer buf.  The fragment reads of the first block
+    // row go out first, so that the products start as soon as they arrive;
+    // the staged tile's LDS stores and the next global loads follow the first
+    // row's products, and each later row's reads are issued one row ahead.
+    // The scheduling fences keep the compiler from hoisting every read (and
+    // the stores) to the top, where the wave would wait for all of them
+    // before its first product.  At most 12 LDS operations are outstanding
+    // when a product waits, so the waits stay partial.
+    static_assert(WM % 2 == 0, "rows are read two ahead in pairs");
+    auto step = [&](int buf, bool do_store, int store_buf, bool do_load, int64_t load_kt) {
+      u4 b[WN][4], a0[4], a1[4];
+      read_a(a0, buf, 0);
+      read_b(b, buf);
+      __builtin_amdgcn_sched_barrier(0);
+      read_a(a1, buf, 1);
+      mma_row(a0, b, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (do_store) store(st, store_buf);
+      if (do_load) load(st, load_kt);
+      __builtin_amdgcn_sched_barrier(0);
+  #pragma unroll
+      for (int i = 1; i < WM; i += 2) {
+        if (i + 1 < WM) read_a(a0, buf, i + 1);
+        mma_row(a1, b, i);
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 2 < WM) read_a(a1, buf, i + 2);
+        if (i + 1 < WM) mma_row(a0, b, i + 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+
+    // LDS buffer t % 2 holds tile t.  The last two tiles are peeled so that
+    // the steady-state body has no branches around its stores and loads.
+    if (ktiles > 0) {
+      load(st, 0);
+      store(st, 0);
+      if (ktiles > 1) load(st, 1);
+    }
+    sync_lds();
+    int64_t kt = 0;
+    for (; kt + 2 < ktiles; ++kt) {
+      step(int(kt & 1), true, int((kt + 1) & 1), true, kt + 2);
+      sync_lds();
+    }
+    if (kt + 1 < ktiles) {
+      step(int(kt & 1), true, int((kt + 1) & 1), false, 0);
+      sync_lds();
+      ++kt;
+    }
+    if (kt < ktiles) step(int(kt & 1), false, 0, false, 0);
   }
 
   split_epilogue<WM, WN>(p, acc_re, acc_im, m0 + wm * WM * 16, n0 + wn * WN * 16,
                          p.herm && tm != tn);
 }
 
-template <int WGM, int WGN, int WM, int WN>
+template <int WGM, int WGN, int WM, int WN, bool PP>
 __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const SplitParams p) {
   __shared__ SplitLds sA, sB;
   int tm, tn;
@@ -378,7 +471,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
     tri_coords(xcd_linear(blockIdx.x, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
   else
     tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
-  split_tile<WGM, WGN, WM, WN>(p, tm, tn, sA, sB);
+  split_tile<WGM, WGN, WM, WN, PP>(p, tm, tn, sA, sB);
 }
 
 // Many split products in one launch, one workgroup per tile of the
@@ -389,7 +482,7 @@ struct SplitItem {
   int tile_begin;
 };
 
-template <int WGM, int WGN, int WM, int WN>
+template <int WGM, int WGN, int WM, int WN, bool PP>
 __global__ void __launch_bounds__(64 * WGM * WGN, 1)
 split_grouped_kernel(const SplitItem* __restrict__ items, int count) {
   __shared__ SplitLds sA, sB;
@@ -405,7 +498,7 @@ split_grouped_kernel(const SplitItem* __restrict__ items, int count) {
   const int first_m = (local / per_group) * GROUP_M;
   const int gsize = min(p.tiles_m - first_m, GROUP_M);
   const int in_group = local % per_group;
-  split_tile<WGM, WGN, WM, WN>(p, first_m + in_group % gsize, in_group / gsize, sA, sB);
+  split_tile<WGM, WGN, WM, WN, PP>(p, first_m + in_group % gsize, in_group / gsize, sA, sB);
 }
 
 // out(r, c) for r < Rp, c < Cp from src (R x C valid, element (r, c) at
@@ -460,8 +553,9 @@ int split_into(const c64* src, int64_t ld, int64_t R, int64_t C, bool trans, boo
   return TC_OK;
 }
 
-// Kernel shape: 0 = 8 waves of 64 x 32 outputs (default), 1 = 4 waves of
-// 64 x 64.  TC_SPLIT_VARIANT selects one for timing.
+// Kernel shape: 0 = 8 waves of 64 x 32 outputs in two ping-pong groups
+// (default), 1 = 4 waves of 64 x 64, 2 = 8 waves of 64 x 32 in lockstep.
+// TC_SPLIT_VARIANT selects one for timing.
 int split_variant() {
   static const int v = [] {
     const char* e = getenv("TC_SPLIT_VARIANT");
@@ -505,9 +599,11 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
   ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
   const dim3 grid{unsigned(tiles), 1u, 1u};
   if (split_variant() == 1)
-    hipLaunchKernelGGL((split_gemm_kernel<2, 2, 4, 4>), grid, dim3(256), 0, s, q);
+    hipLaunchKernelGGL((split_gemm_kernel<2, 2, 4, 4, false>), grid, dim3(256), 0, s, q);
+  else if (split_variant() == 2)
+    hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, false>), grid, dim3(512), 0, s, q);
   else
-    hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2>), grid, dim3(512), 0, s, q);
+    hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, true>), grid, dim3(512), 0, s, q);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -564,8 +660,12 @@ int split_grouped_build(const std::vector<SplitProduct>& ps, void* items_dev, Sp
 int split_grouped_run(const SplitGrouped& g, hipStream_t s) {
   if (g.count == 0 || g.total_tiles == 0) return TC_OK;
   ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
-  hipLaunchKernelGGL((split_grouped_kernel<2, 4, 4, 2>), dim3(unsigned(g.total_tiles)), dim3(512),
-                     0, s, static_cast<const SplitItem*>(g.items_dev), g.count);
+  if (split_variant() == 2)
+    hipLaunchKernelGGL((split_grouped_kernel<2, 4, 4, 2, false>), dim3(unsigned(g.total_tiles)),
+                       dim3(512), 0, s, static_cast<const SplitItem*>(g.items_dev), g.count);
+  else
+    hipLaunchKernelGGL((split_grouped_kernel<2, 4, 4, 2, true>), dim3(unsigned(g.total_tiles)),
+                       dim3(512), 0, s, static_cast<const SplitItem*>(g.items_dev), g.count);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
