@@ -441,11 +441,23 @@ def cpu_baseline(U_np, rho_np, target_s=15.0):
     Small slabs size the final one to about target_s seconds of CPU work."""
     import numpy as np
     from oracle import linalg as olin
+    blas = "numpy BLAS"
     try:
         from threadpoolctl import threadpool_info
-        cores = max((d.get("num_threads", 0) for d in threadpool_info()), default=os.cpu_count())
+        info = threadpool_info()
+        cores = max((d.get("num_threads", 0) for d in info), default=os.cpu_count())
+        libs = [f"{d.get('internal_api', '')} {d.get('version', '')}".strip()
+                for d in info if d.get("user_api") == "blas"]
+        if libs:
+            blas = ", ".join(libs)
     except Exception:
         cores = os.cpu_count()
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     N = U_np.shape[0]
 
     def run(rows):
@@ -464,8 +476,9 @@ def cpu_baseline(U_np, rho_np, target_s=15.0):
         elapsed = run(rows)
     per_step = elapsed * N / rows
     return {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of one N={N} step (U[rows] rho U^dag, numpy/OpenBLAS "
-                      f"complex128), {elapsed:.2f} s, scaled by N/rows"}
+            "sample": f"rows 0..{rows - 1} of one N={N} step (U[rows] rho U^dag, numpy complex128 "
+                      f"products), {elapsed:.2f} s, scaled by N/rows",
+            "cpu": cpu, "blas": blas}
 
 
 def main():
