@@ -136,6 +136,18 @@ __device__ __forceinline__ int xcd_linear(int pid, int total) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
 }
 
+// Tile lists of grouped launches are sorted by decreasing K, so consecutive
+// ids have similar work.  Within each run of 256 ids (one tile per CU), XCD x
+// (id mod 8) takes the 32 consecutive list entries 32 x .. 32 x + 31, so that
+// its concurrent tiles are neighbours of one product that share operand
+// panels in its L2, while every XCD still gets an equal share of each run.
+// Ids past the last whole run keep their place.
+__device__ __forceinline__ int round_xcd(int pid, int total) {
+  const int whole = total - total % 256;
+  if (pid >= whole) return pid;
+  return (pid / 256) * 256 + (pid % 8) * 32 + (pid % 256) / 8;
+}
+
 // Tile lin of the upper block triangle (tm <= tn) of a T x T tile grid:
 // GROUP_M tile rows at a time, column by column within a group.
 __device__ __forceinline__ void tri_coords(int lin, int T, int& tm, int& tn) {
@@ -681,7 +693,7 @@ template <int WGM, int WGN, int WM, int WN, bool PP>
 __global__ void __launch_bounds__(64 * WGM * WGN, 1)
 split_grouped_kernel(const SplitItem* __restrict__ items, int count) {
   __shared__ SplitLds sA, sB;
-  const int t = blockIdx.x;
+  const int t = round_xcd(blockIdx.x, gridDim.x);
   int lo = 0, hi = count - 1;              // last item with tile_begin <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
