@@ -128,6 +128,23 @@ def test_zgemm_split_bf16(M, N, K, op_a, op_b):
     assert np.max(np.abs(got - exact)) <= 3e-5 * math.sqrt(K) * max(scale / math.sqrt(K), 1.0)
 
 
+@pytest.mark.parametrize("M,N,K", [(2048, 2048, 256), (2048, 4096, 96)])
+def test_zgemm_split_bf16_band_order(M, N, K):
+    """Tile grids that are multiples of 16 x 16 tiles take the band order (all
+    XCDs in one 16-row band, each walking its quarter of the columns): every
+    tile is computed exactly once and equals the emulated split product."""
+    A = ti.random_matrix((M, K), 8)
+    B = ti.random_matrix((K, N), 9)
+    Aop, Bop = A.astype(np.complex64), B.astype(np.complex64)
+    emu = split_product_reference(Aop, Bop)
+    C = torch.full((M, N), complex(np.nan, np.nan), dtype=torch.complex128, device=DEV)
+    tcm.tc_zgemm(_dev(A), _dev(B), C, 0, 0, 1.0, 0.0, tcm.TC_GEMM_SPLIT_BF16)
+    got = C.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    scale = np.max(np.abs(emu))
+    assert np.max(np.abs(got - emu)) <= 4e-7 * math.sqrt(K) * max(scale, 1.0)
+
+
 def test_split_bf16_bit_exact():
     rng = np.random.default_rng(5)
     x = (rng.standard_normal(1 << 16) * np.exp(rng.uniform(-30, 30, 1 << 16))).astype(np.float32)
