@@ -378,6 +378,58 @@ def bench_sectors11(tcm, pipeline, ti, steps=40):
     return out
 
 
+def bench_share(tcm, pipeline, ti, reps=4):
+    """One GPU's share of the step distributed over P GPUs by row blocks (rho
+    in blocks of N/P rows, U on every GPU): the two local products of a step,
+    Y_r = rho_r conj(U) ((N/P) x N x N) and U Y_c (N x (N/P) x N, Y_c a block
+    of N/P columns after the all-to-all), in split-BF16 at N = 12288 on the
+    TCM operands, timed by the product kernel's own events.  The all-to-all
+    between them is not run here (one GPU)."""
+    import torch
+    w = ti.get("n11")
+    inst = w.instances[0]
+    m = pipeline.model_of(inst)
+    N, dt = inst.N, w.dt
+    _, U = pipeline.propagator(m, dt)
+    rho = torch.from_numpy(inst.rho0()).to("cuda")
+    kind = tcm.TC_KERNEL_SPLIT_BF16
+    out = {"workload": "tcm_n11_c5_N12288_share", "N": N, "dtype": "bf16",
+           "products": "Y_r = rho_r conj(U), then U Y_c", "shares": []}
+
+    def timed(A, B, C, op_b):
+        tcm.tc_zgemm(A, B, C, 0, op_b, 1.0, 0.0, tcm.TC_GEMM_SPLIT_BF16)
+        torch.cuda.synchronize()
+        tcm.tc_profile_enable(True)
+        for _ in range(reps):
+            tcm.tc_zgemm(A, B, C, 0, op_b, 1.0, 0.0, tcm.TC_GEMM_SPLIT_BF16)
+        torch.cuda.synchronize()
+        kms, kl = tcm.tc_profile_read(kind)
+        tcm.tc_profile_enable(False)
+        return kms / max(1, kl)
+
+    for P in (1, 2, 4, 8):
+        r = N // P
+        rho_r = rho[:r].contiguous()
+        C1 = torch.empty((r, N), dtype=torch.complex128, device="cuda")
+        ms1 = timed(rho_r, U, C1, 1)
+        B2 = rho[:, :r].contiguous()
+        C2 = torch.empty((N, r), dtype=torch.complex128, device="cuda")
+        ms2 = timed(U, B2, C2, 0)
+        fl = 8.0 * r * N * N
+        out["shares"].append({"gpus": P, "rows": r, "rows_product_ms": ms1,
+                              "cols_product_ms": ms2,
+                              "rows_product_tflops": fl / (ms1 * 1e-3) / 1e12,
+                              "cols_product_tflops": fl / (ms2 * 1e-3) / 1e12,
+                              "local_products_ms_per_step": ms1 + ms2})
+        del rho_r, C1, B2, C2
+        torch.cuda.empty_cache()
+    base = out["shares"][0]["local_products_ms_per_step"]
+    for e in out["shares"]:
+        e["compute_speedup_vs_1"] = base / e["local_products_ms_per_step"]
+    del U, rho
+    return out
+
+
 def bench_paper_sweep(tcm, pipeline, ti, ns=range(8, 16)):
     """The paper's own model (the 2^n states of all-excited atoms, Sec. II and
     IV) at N = 2^8 .. 2^15 on one GPU: the time to form L by Eq. (10)'s
@@ -488,7 +540,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="split,fp64,fp32")
-    ap.add_argument("--extras", default="n9,batch64,grad8,open11,dense12,sectors11,paper",
+    ap.add_argument("--extras", default="n9,batch64,grad8,open11,dense12,sectors11,paper,share",
                     help="other workloads measured after the headline one ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
@@ -612,7 +664,8 @@ def main():
     for e in extras:
         fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8,
               "open11": bench_open11, "dense12": bench_dense12,
-              "sectors11": bench_sectors11, "paper": bench_paper_sweep}[e]
+              "sectors11": bench_sectors11, "paper": bench_paper_sweep,
+              "share": bench_share}[e]
         out["other_workloads"][e] = fn(tcm, pipeline, ti)
         log(f"{e}: {out['other_workloads'][e]}")
         torch.cuda.empty_cache()
