@@ -5,6 +5,8 @@
 // Reductions are deterministic: fixed per-thread strides, then a fixed LDS
 // tree inside one workgroup (no atomics), so reruns are bitwise identical.
 #include "kernels.h"
+
+#include <type_traits>
 #include "ham_entry.h"
 
 namespace tcm {
@@ -197,6 +199,61 @@ __global__ void damp_atoms_kernel(E* __restrict__ rho, int64_t ld, int64_t N, in
         const int64_t r = r0 + ((u & 1) ? e[0] : 0) + ((u & 2) ? e[1] : 0);
         const int64_t c = s0 + ((v & 1) ? e[0] : 0) + ((v & 2) ? e[1] : 0);
         rho[r * ld + c] = E{decltype(E::re)(xr[u][v]), decltype(E::re)(xi[u][v])};
+      }
+  }
+}
+
+// Three atoms per pass (bits b0 < b1 < b2) for the complex FP32 state, in
+// FP32 arithmetic (the 8 x 8 block of 64 complex values stays in registers;
+// in FP64 it would not fit): the same channel as above applied for each of
+// the three bits in turn, so a state of n atoms takes ceil(n / 3) passes
+// over the matrix instead of ceil(n / 2).
+__global__ void __launch_bounds__(TPB)
+damp_atoms3_c64_kernel(c64* __restrict__ rho, int64_t ld, int64_t N, int b0, int b1, int b2,
+                       float p, float f) {
+  constexpr int B = 8;
+  const int64_t R = N >> 3;
+  const int64_t qs = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (qs >= R) return;
+  const int64_t s0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qs, b0), b1), b2);
+  const int64_t e0 = int64_t(1) << b0, e1 = int64_t(1) << b1, e2 = int64_t(1) << b2;
+  const float q1 = 1.f - p;
+  for (int64_t qr = blockIdx.y; qr < R; qr += gridDim.y) {
+    const int64_t r0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qr, b0), b1), b2);
+    float xr[B][B], xi[B][B];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int v = 0; v < B; ++v) {
+        const int64_t r = r0 + ((u & 1) ? e0 : 0) + ((u & 2) ? e1 : 0) + ((u & 4) ? e2 : 0);
+        const int64_t c = s0 + ((v & 1) ? e0 : 0) + ((v & 2) ? e1 : 0) + ((v & 4) ? e2 : 0);
+        const c64 x = rho[r * ld + c];
+        xr[u][v] = x.re;
+        xi[u][v] = x.im;
+      }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int bit = 1 << k;
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int v = 0; v < B; ++v) {
+          if ((u & bit) || (v & bit)) continue;
+          const int u1 = u | bit, v1 = v | bit;
+          xr[u][v] += p * xr[u1][v1];
+          xi[u][v] += p * xi[u1][v1];
+          xr[u][v1] *= f; xi[u][v1] *= f;
+          xr[u1][v] *= f; xi[u1][v] *= f;
+          xr[u1][v1] *= q1; xi[u1][v1] *= q1;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int v = 0; v < B; ++v) {
+        const int64_t r = r0 + ((u & 1) ? e0 : 0) + ((u & 2) ? e1 : 0) + ((u & 4) ? e2 : 0);
+        const int64_t c = s0 + ((v & 1) ? e0 : 0) + ((v & 2) ? e1 : 0) + ((v & 4) ? e2 : 0);
+        rho[r * ld + c] = c64{xr[u][v], xi[u][v]};
       }
   }
 }
@@ -731,7 +788,16 @@ int launch_dissipation_t(const ModelArgs& m, E* rho, int64_t ld, double dt, hipS
   if (m.gamma > 0.0) {
     const double p = -expm1(-m.gamma * dt);        // 1 - e^{-gamma dt}
     const double f = sqrt(1.0 - p);
-    for (int b = 0; b < m.n; b += 2) {
+    int b = 0;
+    if constexpr (std::is_same<E, c64>::value) {
+      for (; b + 3 <= m.n; b += 3) {
+        const int64_t R = m.N >> 3;
+        hipLaunchKernelGGL(damp_atoms3_c64_kernel, grid2(R, R), dim3(TPB), 0, s, rho, ld, m.N, b,
+                           b + 1, b + 2, float(p), float(f));
+        TC_TRY_HIP(hipGetLastError());
+      }
+    }
+    for (; b < m.n; b += 2) {
       if (b + 1 < m.n) {
         const int64_t R = m.N >> 2;
         hipLaunchKernelGGL((damp_atoms_kernel<E, 2>), grid2(R, R), dim3(TPB), 0, s, rho, ld, m.N,
