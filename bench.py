@@ -527,10 +527,24 @@ def cpu_baseline(U_np, rho_np, target_s=15.0):
         rows = int(min(N, max(rows, rows * target_s / elapsed // 64 * 64)))
         elapsed = run(rows)
     per_step = elapsed * N / rows
-    return {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of one N={N} step (U[rows] rho U^dag, numpy complex128 "
-                      f"products), {elapsed:.2f} s, scaled by N/rows",
-            "cpu": cpu, "blas": blas}
+    out = {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"rows 0..{rows - 1} of one N={N} step (U[rows] rho U^dag, numpy complex128 "
+                     f"products), {elapsed:.2f} s, scaled by N/rows",
+           "cpu": cpu, "blas": blas}
+    # the same on one core, on a slab sized to about a third of target_s
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            r1 = 64
+            t1 = run(r1)
+            r1 = int(min(N, max(64, r1 * (target_s / 3.0) / t1 // 64 * 64)))
+            t1 = run(r1)
+        out["single_core"] = {"value": 1.0 / (t1 * N / r1), "unit": "steps/s",
+                              "sample": f"rows 0..{r1 - 1}, {t1:.2f} s on 1 thread, "
+                                        f"scaled by N/rows"}
+    except Exception as e:   # threadpoolctl missing or unable to limit the BLAS
+        out["single_core"] = {"value": None, "note": f"not measured: {e}"}
+    return out
 
 
 def main():
