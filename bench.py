@@ -63,11 +63,11 @@ def traffic_entry(kernel, workload, src):
 TILE = 128                # output tile edge of the product kernels at this size
 
 
-def executed_flop_per_step(N, full=False):
+def executed_flop_per_step(N, full=False, tile=TILE):
     """Flops (8 per complex multiply-add) the two products of one step execute:
     the first product in full; the second, whose result is Hermitian, on the
     T(T+1)/2 tiles on and above the tile diagonal of its T x T tile grid."""
-    T = -(-N // TILE)
+    T = -(-N // tile)
     frac = 1.0 if full else T * (T + 1) / 2.0 / (T * T)
     return 8.0 * float(N) ** 3 * (1.0 + frac)
 
@@ -121,9 +121,40 @@ def bench_n9(tcm, pipeline, ti, steps=100):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    fx = executed_flop_per_step(inst.N)
     return {"workload": w.name, "N": inst.N, "dtype": "f64", "steps": steps,
             "steps_per_s": 1000.0 / ms, "ms_per_step": ms,
-            "tflops": 16.0 * inst.N ** 3 / (ms * 1e-3) / 1e12}
+            "tflops": 16.0 * inst.N ** 3 / (ms * 1e-3) / 1e12,
+            "tflops_executed": fx / (ms * 1e-3) / 1e12,
+            "executed_frac_of_peak": fx / (ms * 1e-3) / PEAK_F64}
+
+
+def bench_jc3(tcm, pipeline, ti):
+    """n = 3, c = 3 (N = 32), FP64, dt = 0.01 x 1000 steps with the excited-atom
+    population recorded every step: launch-bound.  Timed with the launches of
+    every step issued eagerly and as hipGraph-captured chunks."""
+    import torch
+    w = ti.get("jc3")
+    inst = w.instances[0]
+    m = pipeline.model_of(inst)
+    _, U = pipeline.propagator(m, w.dt)
+    rho0 = torch.from_numpy(inst.rho0()).to("cuda")
+    out = {"workload": w.name, "N": inst.N, "dtype": "f64", "steps": w.steps}
+    for key, graph in (("eager", False), ("graph", True)):
+        pipeline.evolve(m, U, rho0.clone(), 50, w.dt, use_graph=graph)     # warm-up
+        rho = rho0.clone()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        pop, _, _ = pipeline.evolve(m, U, rho, w.steps, w.dt, use_graph=graph)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        out[key] = {"ms_total": ms, "wall_ms": 1e3 * wall, "steps_per_s": w.steps / (ms * 1e-3),
+                    "us_per_step": 1e3 * ms / w.steps, "final_excitation": float(pop[-1].item())}
+    return out
 
 
 def bench_batch64(tcm, pipeline, ti, steps=50):
@@ -157,9 +188,17 @@ def bench_batch64(tcm, pipeline, ti, steps=50):
     run(16)                                                      # warm-up
     ms = run(steps)
     flop = 16.0 * sum(float(m.N) ** 3 for m in models) * steps
+    edge = {b: 128 if tcm.tc_autotune_query(tcm.TC_GEMM_F32, b) == 1 else 64
+            for b in (256, 1024, 4096, 1 << 30)}
+
+    def tile_edge(N):
+        return edge[min(b for b in edge if N <= b)]
+    fx = sum(executed_flop_per_step(m.N, tile=tile_edge(m.N)) for m in models) * steps
     out = {"workload": w.name, "instances": len(models), "N_min": min(m.N for m in models),
            "N_max": maxN, "dtype": "f32", "steps": steps, "steps_per_s": steps / (ms * 1e-3),
            "ms_per_step": ms / steps, "tflops": flop / (ms * 1e-3) / 1e12,
+           "tflops_executed": fx / (ms * 1e-3) / 1e12,
+           "executed_frac_of_peak": fx / (ms * 1e-3) / PEAK_F32,
            "autotune_s": tune_s,
            "tile_variants": {str(b): tcm.tc_autotune_query(tcm.TC_GEMM_F32, b)
                              for b in (256, 1024, 4096, 7168)}}
@@ -477,6 +516,10 @@ def bench_paper_sweep(tcm, pipeline, ti, ns=range(8, 16)):
             row[key + "_ms_per_step"] = ms
             row[key + "_steps"] = steps
             row[key + "_tflops"] = 16.0 * D ** 3 / (ms * 1e-3) / 1e12
+            fx = executed_flop_per_step(D, tile=128)
+            row[key + "_tflops_executed"] = fx / (ms * 1e-3) / 1e12
+            row[key + "_executed_frac_of_peak"] = (
+                fx / (ms * 1e-3) / (PEAK_F64 if key == "fp64" else PEAK_BF16 / 3.0))
             row[key + "_final_excitation"] = float(pop[-1].item())
             del rho
         del L
@@ -487,63 +530,119 @@ def bench_paper_sweep(tcm, pipeline, ti, ns=range(8, 16)):
             "rows": rows}
 
 
-def cpu_baseline(U_np, rho_np, target_s=15.0):
-    """The oracle's dense step (U rho U^dag with numpy products) on a row slab of
-    the same N = 12288 matrices, timed on the host cores; scaled to steps/s.
-    Small slabs size the final one to about target_s seconds of CPU work."""
-    import numpy as np
+def _host_cpu():
+    """The host CPU as the OS names it: /proc/cpuinfo's model name, with the
+    vendor, family, model and stepping numbers (a short model name alone may
+    not say which part it is)."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    if info:
+                        break
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "vendor_id", "cpu family", "model", "stepping") \
+                        and k not in info:
+                    info[k] = v
+    except OSError:
+        pass
+    name = info.get("model name", "unknown")
+    return (f"{name} ({info.get('vendor_id', '?')} family {info.get('cpu family', '?')} "
+            f"model {info.get('model', '?')} stepping {info.get('stepping', '?')})")
+
+
+def cpu_baseline(U_np, rho_np, min_s=20.0):
+    """The oracle's dense step (rho <- U rho U^dag, numpy complex128 products on
+    the host BLAS) on the N = 12288 matrices of the timed workload: whole steps,
+    after a warm-up product on a row slab, until at least min_s seconds have
+    passed (two steps on 16 threads).  One host thread is timed on a row slab
+    of one step, scaled by N / rows, and labelled so."""
     from oracle import linalg as olin
-    blas = "numpy BLAS"
+    blas, threads = "numpy BLAS", None
     try:
         from threadpoolctl import threadpool_info
         info = threadpool_info()
-        cores = max((d.get("num_threads", 0) for d in info), default=os.cpu_count())
+        threads = max((d.get("num_threads", 0) for d in info if d.get("user_api") == "blas"),
+                      default=None)
         libs = [f"{d.get('internal_api', '')} {d.get('version', '')}".strip()
                 for d in info if d.get("user_api") == "blas"]
         if libs:
             blas = ", ".join(libs)
     except Exception:
-        cores = os.cpu_count()
-    cpu = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
-    except OSError:
         pass
+    affinity = len(os.sched_getaffinity(0))
     N = U_np.shape[0]
-
-    def run(rows):
-        t0 = time.perf_counter()
-        X = olin.gemm(U_np[:rows], rho_np)          # rows x N
-        olin.gemm(X, U_np, op_b="h")                # rows x N of U rho U^dag
-        return time.perf_counter() - t0
-
-    rows = 64
-    elapsed = run(rows)
-    while elapsed < 1.0 and rows < N:
-        rows = min(N, rows * 4)
-        elapsed = run(rows)
-    if rows < N:
-        rows = int(min(N, max(rows, rows * target_s / elapsed // 64 * 64)))
-        elapsed = run(rows)
-    per_step = elapsed * N / rows
-    out = {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"rows 0..{rows - 1} of one N={N} step (U[rows] rho U^dag, numpy complex128 "
-                     f"products), {elapsed:.2f} s, scaled by N/rows",
-           "cpu": cpu, "blas": blas}
-    # the same on one core, on a slab sized to about a third of target_s
+    olin.gemm(U_np[:512], rho_np)                       # warm-up: BLAS threads up
+    steps, t0 = 0, time.perf_counter()
+    rho = rho_np
+    while True:
+        X = olin.gemm(U_np, rho)
+        rho = olin.gemm(X, U_np, op_b="h")
+        del X
+        steps += 1
+        elapsed = time.perf_counter() - t0
+        if elapsed >= min_s:
+            break
+    out = {"value": steps / elapsed, "unit": "steps/s",
+           "cores": int(threads) if threads else affinity, "kind": "oracle",
+           "sample": f"{steps} whole steps of the N={N} workload (U rho U^dag, numpy complex128 "
+                     f"products, 16 N^3 = {16.0 * N ** 3:.3g} flop each) after a 512-row "
+                     f"warm-up product, {elapsed:.2f} s",
+           "s_per_step": elapsed / steps,
+           "gflops": 16.0 * N ** 3 * steps / elapsed / 1e9,
+           "blas_threads": threads, "affinity_cpus": affinity,
+           "cpu": _host_cpu(), "blas": blas}
+    del rho
+    # one thread, on a row slab of one step sized to about 8 s
     try:
         from threadpoolctl import threadpool_limits
+
+        def slab(rows):
+            t = time.perf_counter()
+            X = olin.gemm(U_np[:rows], rho_np)
+            olin.gemm(X, U_np, op_b="h")
+            return time.perf_counter() - t
         with threadpool_limits(limits=1):
             r1 = 64
-            t1 = run(r1)
-            r1 = int(min(N, max(64, r1 * (target_s / 3.0) / t1 // 64 * 64)))
-            t1 = run(r1)
+            t1 = slab(r1)
+            r1 = int(min(N, max(64, r1 * 8.0 / t1 // 64 * 64)))
+            t1 = slab(r1)
         out["single_core"] = {"value": 1.0 / (t1 * N / r1), "unit": "steps/s",
-                              "sample": f"rows 0..{r1 - 1}, {t1:.2f} s on 1 thread, "
-                                        f"scaled by N/rows"}
+                              "sample": f"rows 0..{r1 - 1} of one step, {t1:.2f} s on 1 thread, "
+                                        f"scaled by N/rows (extrapolated, not a whole step)"}
     except Exception as e:   # threadpoolctl missing or unable to limit the BLAS
         out["single_core"] = {"value": None, "note": f"not measured: {e}"}
+    return out
+
+
+def parity_errors(inst, dt, runs):
+    """Max-entry and population error of each timed run against the oracle's
+    exact evolution of the same pure state (per-sector eigendecomposition of
+    H), after the same number of steps: max_ij |rho_ij - psi_i conj(psi_j)|
+    over the whole final matrix and max over every record of
+    |sum_i <s_i^+ s_i^-> - oracle|."""
+    import numpy as np
+    from oracle import evolve as oev
+    from oracle import model as omodel
+    P = oev.SectorPropagator(inst.n, inst.c, inst.g, inst.omega_a)
+    O = sum(omodel.atom_excitation_diag(inst.n, inst.c, i) for i in range(inst.n))
+    out = {}
+    for key, (rho_dev, pop_dev, steps) in runs.items():
+        psi = P.psi(inst.psi0, steps * dt)
+        rho = rho_dev.cpu().numpy()
+        err = 0.0
+        for r0 in range(0, psi.size, 1024):
+            blk = rho[r0:r0 + 1024].astype(np.complex128)
+            err = max(err, float(np.max(np.abs(blk - np.outer(psi[r0:r0 + 1024], psi.conj())))))
+        del rho
+        pop = pop_dev.cpu().numpy()
+        perr = max(abs(pop[k] - float(np.sum(O * np.abs(P.psi(inst.psi0, k * dt)) ** 2)))
+                   for k in range(steps + 1))
+        out[key] = {"steps": steps, "max_entry": err, "population": perr,
+                    "bar": 1e-10 if key == "fp64" else 1e-5}
+        log(f"{key}: max-entry error {err:.3e}, population error {perr:.3e} after {steps} steps")
     return out
 
 
@@ -554,7 +653,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="split,fp64,fp32")
-    ap.add_argument("--extras", default="n9,batch64,grad8,open11,dense12,sectors11,paper,share",
+    ap.add_argument("--extras", default="jc3,n9,batch64,grad8,open11,dense12,sectors11,paper,share",
                     help="other workloads measured after the headline one ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
@@ -651,32 +750,49 @@ def main():
     out["expm_s"] = expm_s
 
     # roofline of the dominant kernel (the complex product), from live events:
-    # the launches alternate between the full first product and the triangle
-    # of the second, so a launch executes flop_exec / 2 on average
+    # a launch is one complex N x N x N product, 8 N^3 flop on the method's
+    # count; the launches alternate between the full first product and the
+    # upper tile triangle of the second, so a launch executes flop_exec / 2 on
+    # average, and the split form issues three BF16 products per real product
     kern_ms = hs["product_kernel_ms"]
-    per_launch_flop = flop_exec / 2.0
-    achieved = per_launch_flop / (kern_ms * 1e-3)
+    per_launch_alg = 8.0 * float(N) ** 3
+    per_launch_exec = flop_exec / 2.0
+    achieved = per_launch_alg / (kern_ms * 1e-3)
     peak = {"split": PEAK_BF16, "fp64": PEAK_F64, "fp32": PEAK_F32}[head]
     src = os.path.join(ROOT, "paper_2403_06937_amd", "csrc",
                        "gemm_bf16.hip" if head == "split" else "gemm_mfma.hip")
     kname = "split_gemm_kernel" if head == "split" else "gemm_kernel"
+    exec_frac = per_launch_exec / (kern_ms * 1e-3) / peak
     out["roofline"] = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                        "unit": "TFLOP/s", "frac": achieved / peak,
                        "traffic": traffic_entry(kname, w.name, src),
                        "kernel": kname, "kernel_ms": kern_ms,
-                       "issued_frac": (3.0 * achieved / peak) if head == "split" else achieved / peak}
+                       "algorithmic_flop_per_launch": per_launch_alg,
+                       "executed_flop_per_launch": per_launch_exec,
+                       "executed_frac": exec_frac,
+                       "issued_frac": (3.0 if head == "split" else 1.0) * exec_frac}
 
     if not args.no_cpu:
+        # the CPU leg, the one part of the benchmark that runs the oracle: first
+        # the errors of the timed runs against its exact evolution, then its own
+        # dense step timed on the host cores
+        out["error"] = parity_errors(inst, dt, {k: (res[k]["rho"], res[k]["pop"],
+                                                    K if k == "split" else res[k]["steps"])
+                                                for k in res})
+        for k in list(res):
+            del res[k]["rho"], res[k]["pop"]
+        torch.cuda.empty_cache()
         U_np = U.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(U_np, rho0)
         del U_np
+    res.clear()
     del U
     torch.cuda.empty_cache()
     extras = [e for e in args.extras.split(",") if e]
     if extras:
         out["other_workloads"] = {}
     for e in extras:
-        fn = {"n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8,
+        fn = {"jc3": bench_jc3, "n9": bench_n9, "batch64": bench_batch64, "grad8": bench_grad8,
               "open11": bench_open11, "dense12": bench_dense12,
               "sectors11": bench_sectors11, "paper": bench_paper_sweep,
               "share": bench_share}[e]

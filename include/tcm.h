@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TC_VERSION 110
+#define TC_VERSION 120
 
 /* Status codes. */
 #define TC_OK                     0
@@ -169,8 +169,15 @@ typedef struct {
   void* rho;                /* device N x N, type opts.rho_dtype; in: rho(0), out: rho(steps) */
   int64_t ldr;
   double* pop_out;          /* device [steps/record_every + 1] or NULL: sum_i <s_i^+ s_i^-> */
-  double* photon_dist_out;  /* device [steps/record_every + 1][c + 1] or NULL: P(m)  */
+  double* photon_dist_out;  /* device [steps/record_every + 1][c + 1] or NULL: photon-number
+                               distribution, sum of rho_ss over the states with m photons */
   void* checkpoints;        /* device [steps/checkpoint_every + 1][N][N] of rho_dtype, or NULL */
+  double* photon_state_out; /* device [steps/record_every + 1][min(n, c) + 1] or NULL:
+                               P({m>) of Sec. IV, Eq. (13), read on the sector of the
+                               all-excited start: the sum of rho_ss over the states with
+                               m photons and n - m excited atoms (m = 0 .. min(n, c));
+                               equals photon_dist_out[m] only while rho lies in the
+                               excitation-n sector                                  */
 } tc_instance;
 
 typedef struct {
@@ -183,7 +190,12 @@ typedef struct {
                                after every renorm_every-th step                      */
   int32_t record_every;     /* >= 1 when pop_out / photon_dist_out are given        */
   int32_t checkpoint_every; /* 0 = none; else rho after every checkpoint_every-th step */
-  int32_t use_graph;        /* capture the per-chunk launches in a hipGraph         */
+  int32_t use_graph;        /* 1: the launches of a chunk of steps (a whole number of
+                               periods lcm(record_every, renorm_every), about 16
+                               steps) are captured once in a hipGraph and replayed,
+                               single instances and batches alike; the leftover
+                               steps run eagerly.  Ignored with checkpoints or
+                               fewer steps than a chunk.  Same results bit for bit */
   int32_t full_product;     /* 0: rho' = X U^dag is Hermitian, so its upper tile
                                triangle is multiplied and mirrored (rho(0) must be
                                Hermitian); 1: every tile of both products        */
@@ -238,19 +250,30 @@ int tc_evolve_sector(const tc_instance* inst, int32_t k, const tc_evolve_opts* o
 
 /* ------------------------------------------------ a5/a7: observables */
 
-/* Readout of one density matrix (device, N x N, ldr, type rho_dtype).
+/* Readout of one density matrix (device, N x N, ldr, type rho_dtype): the
+ * expectations Tr(O rho) of the diagonal operators of Eq. (4)'s model, the
+ * invariants of Eq. (6)'s unitary step (trace, purity, Hermiticity, the
+ * excitation-number distribution) and both readings of the {m> probability of
+ * Sec. IV, Eq. (13), whose normalisation factors the paper leaves open.
  * scalars (device [8]): Re Tr, Im Tr, purity sum |rho_ij|^2, max |rho - rho^dag|,
  *   sum_i <s_i^+ s_i^->, <a^dag a>, <N_exc>, non-finite flag (1.0 if any entry
  *   is NaN/Inf).  Diagonal readouts use Re rho_ss.
  * atom_pop (device [n]) p_i, photon_dist (device [c + 1]) P(m),
- * exc_dist (device [n + c + 1]) P_k: each may be NULL.
+ * exc_dist (device [n + c + 1]) P_k,
+ * photon_state (device [min(n, c) + 1]) Eq. (13) on the sector: sum of rho_ss
+ *   over the states with m photons and n - m excited atoms,
+ * dicke (device [min(n, c) + 1]) Eq. (13) on the symmetric state: <v_m| rho |v_m>
+ *   with v_m = binom(n, m)^(-1/2) times the sum of those same basis states, i.e.
+ *   the sum of Re rho_st over pairs of them divided by binom(n, m) (equal to
+ *   photon_state[m] only when rho has no coherence between them);
+ * each output but scalars may be NULL.
  * ws: device workspace of tc_observables_workspace_size bytes (partial sums;
  * the reductions run in a fixed order, so reruns are bitwise identical). */
 int tc_observables_workspace_size(int64_t N, size_t* bytes);
 int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype,
                    int64_t N, int64_t ldr, double* scalars, double* atom_pop,
-                   double* photon_dist, double* exc_dist,
-                   void* ws, size_t ws_bytes, void* stream);
+                   double* photon_dist, double* exc_dist, double* photon_state,
+                   double* dicke, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------- a9: differentiation */
 

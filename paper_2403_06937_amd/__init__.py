@@ -81,7 +81,7 @@ class tc_instance(ctypes.Structure):
                 ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
                 ("rho", ctypes.c_void_p), ("ldr", ctypes.c_int64),
                 ("pop_out", ctypes.c_void_p), ("photon_dist_out", ctypes.c_void_p),
-                ("checkpoints", ctypes.c_void_p)]
+                ("checkpoints", ctypes.c_void_p), ("photon_state_out", ctypes.c_void_p)]
 
 
 class tc_evolve_opts(ctypes.Structure):
@@ -118,7 +118,8 @@ def lib():
             "tc_evolve_workspace_size": [P(tc_instance), i32, P(tc_evolve_opts), P(sz)],
             "tc_evolve": [P(tc_instance), i32, P(tc_evolve_opts), vp, sz, vp],
             "tc_observables_workspace_size": [i64, P(sz)],
-            "tc_observables": [P(tc_model), vp, i32, i64, i64, vp, vp, vp, vp, vp, sz, vp],
+            "tc_observables": [P(tc_model), vp, i32, i64, i64, vp, vp, vp, vp, vp, vp, vp, sz,
+                               vp],
             "tc_evolve_backward_workspace_size": [P(tc_model), i64, P(tc_evolve_opts), P(sz)],
             "tc_evolve_backward": [P(tc_model), vp, i64, vp, i64, i64, P(tc_evolve_opts), vp,
                                    i32, vp, vp, vp, vp, sz, vp],
@@ -247,9 +248,11 @@ def make_opts(steps, dt, gemm_mode=TC_GEMM_F64, rho_dtype=TC_C128, frame=TC_FRAM
                           int(sectors))
 
 
-def make_instance(model: Model, U, rho, pop_out=None, photon_dist_out=None, checkpoints=None):
+def make_instance(model: Model, U, rho, pop_out=None, photon_dist_out=None, checkpoints=None,
+                  photon_state_out=None):
     return tc_instance(ctypes.pointer(model.struct), model.N, _ptr(U), U.stride(0), _ptr(rho),
-                       rho.stride(0), _ptr(pop_out), _ptr(photon_dist_out), _ptr(checkpoints))
+                       rho.stride(0), _ptr(pop_out), _ptr(photon_dist_out), _ptr(checkpoints),
+                       _ptr(photon_state_out))
 
 
 def tc_evolve_workspace_size(instances, opts) -> int:
@@ -324,7 +327,7 @@ def tc_observables_workspace_size(N: int) -> int:
 
 
 def tc_observables(model: Model, rho, scalars, atom_pop=None, photon_dist=None, exc_dist=None,
-                   ws=None, stream=None):
+                   photon_state=None, dicke=None, ws=None, stream=None):
     import torch
     dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
     N = rho.shape[0]
@@ -332,7 +335,8 @@ def tc_observables(model: Model, rho, scalars, atom_pop=None, photon_dist=None, 
         ws = _workspace(tc_observables_workspace_size(N), rho.device)
     _check(lib().tc_observables(ctypes.byref(model.struct), _ptr(rho), dtype, N, rho.stride(0),
                                 _ptr(scalars), _ptr(atom_pop), _ptr(photon_dist),
-                                _ptr(exc_dist), _ptr(ws), ws.numel(), _stream(stream)),
+                                _ptr(exc_dist), _ptr(photon_state), _ptr(dicke), _ptr(ws),
+                                ws.numel(), _stream(stream)),
            "tc_observables")
 
 

@@ -2,8 +2,9 @@
 // helpers of the matrix exponential, frame changes, per-step diagonal readout,
 // FP64 renormalisation, full observables and the bfloat16 split.
 //
-// Reductions are deterministic: fixed per-thread strides, then a fixed LDS
-// tree inside one workgroup (no atomics), so reruns are bitwise identical.
+// Reductions are deterministic: fixed per-thread strides, a butterfly of
+// cross-lane exchanges inside each wavefront, then the wave results added in
+// a fixed order (no atomics), so reruns are bitwise identical.
 #include "kernels.h"
 
 #include <type_traits>
@@ -16,28 +17,39 @@ constexpr int TPB = 256;
 
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 
-// Block-wide sum (all threads get the result).
+// Wavefront sum by a butterfly of cross-lane exchanges: every lane ends with
+// the same bits (each exchange adds the same two values, and IEEE addition
+// commutes).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide sum (all threads get the result): a wavefront sum per wave, then
+// the TPB / 64 wave results added in wave order.
 __device__ double block_sum(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if (t < w) sh[t] += sh[t + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < TPB / 64; ++w) r += sh[w];
   __syncthreads();
   return r;
 }
 __device__ double block_max(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
-    __syncthreads();
-  }
-  const double r = sh[0];
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < TPB / 64; ++w) r = fmax(r, sh[w]);
   __syncthreads();
   return r;
 }
@@ -339,27 +351,35 @@ __global__ void damp_cavity_reg_kernel(E* __restrict__ rho, int64_t ld, int n, i
 // map == NULL: rho is in the basis order; else basis state s sits at row and
 // column map[s] of rho (the excitation-sorted order of the sector stepper, or
 // the order of one sector, where states outside it have map[s] = -1).
+// Writes pop = sum_s |l(s)| Re rho_ss, pdist[m] = sum_{photon(s) = m} Re rho_ss
+// and pstate[m] = P({m>) of Eq. (13) (m photons and n - m excited atoms),
+// m = 0 .. min(n, c); each output may be NULL.
 template <typename E>
-__global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t ld,
-                               const int32_t* __restrict__ map,
-                               double* __restrict__ pop, double* __restrict__ pdist) {
-  __shared__ double sh[TPB];
-  const int n = m.n;
+__device__ __forceinline__ void readout_body(int n, int c, const E* __restrict__ rho, int64_t ld,
+                                             const int32_t* __restrict__ map,
+                                             double* __restrict__ pop, double* __restrict__ pdist,
+                                             double* __restrict__ pstate, double* sh) {
   const int64_t per = int64_t(1) << n;
   const uint64_t mask = uint64_t(per - 1);
   double tot = 0.0;
-  for (int mm = 0; mm <= m.c; ++mm) {
-    double part = 0.0, ex = 0.0;
+  for (int mm = 0; mm <= c; ++mm) {
+    double part = 0.0, ex = 0.0, st = 0.0;
     for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
       const int64_t q = map ? int64_t(map[s]) : s;
       if (q < 0) continue;                     // state outside a one-sector rho
       const double d = double(rho[q * ld + q].re);
+      const int pc = popc64(uint64_t(s) & mask);
       part += d;
-      ex += double(popc64(uint64_t(s) & mask)) * d;
+      ex += double(pc) * d;
+      if (pc == n - mm) st += d;
     }
     if (pdist) {
       const double pm = block_sum(part, sh);
       if (threadIdx.x == 0) pdist[mm] = pm;
+    }
+    if (pstate && mm <= n) {
+      const double pm = block_sum(st, sh);
+      if (threadIdx.x == 0) pstate[mm] = pm;
     }
     tot += ex;
   }
@@ -368,33 +388,23 @@ __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t l
 }
 
 template <typename E>
+__global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t ld,
+                               const int32_t* __restrict__ map, double* __restrict__ pop,
+                               double* __restrict__ pdist, double* __restrict__ pstate) {
+  __shared__ double sh[TPB / 64];
+  readout_body(m.n, m.c, rho, ld, map, pop, pdist, pstate, sh);
+}
+
+template <typename E>
 __global__ void grouped_readout_kernel(const ReadoutItem* __restrict__ items,
                                        const int* __restrict__ counter) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   const ReadoutItem it = items[blockIdx.x];
-  const int r = *counter;
-  const E* __restrict__ rho = static_cast<const E*>(it.rho);
-  const int n = it.n;
-  const int64_t per = int64_t(1) << n;
-  const uint64_t mask = uint64_t(per - 1);
-  double tot = 0.0;
-  for (int mm = 0; mm <= it.c; ++mm) {
-    double part = 0.0, ex = 0.0;
-    for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB) {
-      const int64_t q = it.map ? int64_t(it.map[s]) : s;
-      if (q < 0) continue;
-      const double d = double(rho[q * it.ld + q].re);
-      part += d;
-      ex += double(popc64(uint64_t(s) & mask)) * d;
-    }
-    if (it.pdist) {
-      const double pm = block_sum(part, sh);
-      if (threadIdx.x == 0) it.pdist[int64_t(r) * (it.c + 1) + mm] = pm;
-    }
-    tot += ex;
-  }
-  const double t = block_sum(tot, sh);
-  if (threadIdx.x == 0 && it.pop) it.pop[r] = t;
+  const int64_t r = *counter;
+  const int ns = (it.n < it.c ? it.n : it.c) + 1;
+  readout_body(it.n, it.c, static_cast<const E*>(it.rho), it.ld, it.map,
+               it.pop ? it.pop + r : nullptr, it.pdist ? it.pdist + r * (it.c + 1) : nullptr,
+               it.pstate ? it.pstate + r * ns : nullptr, sh);
 }
 
 __global__ void advance_counter_kernel(int* counter) {
@@ -404,7 +414,7 @@ __global__ void advance_counter_kernel(int* counter) {
 // ---------------------------------------------------- FP64 renormalisation
 template <typename E>
 __global__ void trace_kernel(const E* __restrict__ rho, int64_t ld, int64_t N, double* scratch) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   double part = 0.0;
   for (int64_t s = threadIdx.x; s < N; s += TPB) part += double(rho[s * ld + s].re);
   const double tr = block_sum(part, sh);
@@ -465,7 +475,7 @@ __global__ void obs_pass1(const E* __restrict__ rho, int64_t ld, int64_t N,
                           double* __restrict__ partials, double* __restrict__ diag) {
   __shared__ double2 tA[RT][RT + 1];
   __shared__ double2 tB[RT][RT + 1];
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   int64_t bi, bj;
   pair_index(blockIdx.x, bi, bj);
   const int tx = threadIdx.x % RT, ty = threadIdx.x / RT;
@@ -505,8 +515,9 @@ __global__ void obs_pass1(const E* __restrict__ rho, int64_t ld, int64_t N,
 __global__ void obs_pass2(ModelArgs m, const double* __restrict__ partials, int64_t npairs,
                           const double* __restrict__ diag, const double* __restrict__ trace_im_src,
                           double* __restrict__ scalars, double* __restrict__ atom_pop,
-                          double* __restrict__ photon_dist, double* __restrict__ exc_dist) {
-  __shared__ double sh[TPB];
+                          double* __restrict__ photon_dist, double* __restrict__ exc_dist,
+                          double* __restrict__ photon_state) {
+  __shared__ double sh[TPB / 64];
   const int n = m.n;
   const int64_t N = m.N;
   const uint64_t mask = (uint64_t(1) << n) - 1;
@@ -561,6 +572,17 @@ __global__ void obs_pass2(ModelArgs m, const double* __restrict__ partials, int6
       if (threadIdx.x == 0) photon_dist[mm] = p;
     }
   }
+  if (photon_state) {
+    // Eq. (13), sector reading: m photons and n - m excited atoms
+    const int64_t per = int64_t(1) << n;
+    for (int mm = 0; mm <= m.c && mm <= n; ++mm) {
+      double p = 0.0;
+      for (int64_t s = mm * per + threadIdx.x; s < (mm + 1) * per; s += TPB)
+        if (popc64(uint64_t(s) & mask) == n - mm) p += diag[s];
+      p = block_sum(p, sh);
+      if (threadIdx.x == 0) photon_state[mm] = p;
+    }
+  }
   if (exc_dist) {
     for (int k = 0; k <= n + m.c; ++k) {
       double p = 0.0;
@@ -572,10 +594,55 @@ __global__ void obs_pass2(ModelArgs m, const double* __restrict__ partials, int6
   }
 }
 
+// Eq. (13), symmetric reading: <v_m| rho |v_m> with v_m the normalised equal
+// sum of the binom(n, m) basis states with m photons and n - m excited atoms,
+// i.e. the sum of Re rho_st over those pairs divided by binom(n, m).
+// Pass 1: grid (ceil(2^n / 4), min(n, c) + 1); wave w of block b takes atom
+// pattern l = 4 b + w as its row and sums its row of the photon block m over
+// the columns with the same excitation count; partials[m * gridDim.x + b].
+template <typename E>
+__global__ void dicke_pass1(int n, const E* __restrict__ rho, int64_t ld,
+                            double* __restrict__ partials) {
+  __shared__ double sh[TPB / 64];
+  const int mm = blockIdx.y;
+  const int64_t per = int64_t(1) << n;
+  const int64_t l = int64_t(blockIdx.x) * (TPB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  if (l < per && popc64(uint64_t(l)) == n - mm) {
+    const E* row = rho + (mm * per + l) * ld + mm * per;
+    for (int64_t t = lane; t < per; t += 64)
+      if (popc64(uint64_t(t)) == n - mm) acc += double(row[t].re);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < TPB / 64; ++w) r += sh[w];
+    partials[int64_t(mm) * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// Pass 2: one block per m: dicke[m] = (sum of its partials) / binom(n, m).
+__global__ void dicke_pass2(int n, const double* __restrict__ partials, int64_t nblk,
+                            double* __restrict__ dicke) {
+  __shared__ double sh[TPB / 64];
+  const int mm = blockIdx.x;
+  double p = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += TPB) p += partials[int64_t(mm) * nblk + b];
+  p = block_sum(p, sh);
+  if (threadIdx.x == 0) {
+    double binom = 1.0;
+    for (int j = 1; j <= mm; ++j) binom = binom * double(n - mm + j) / double(j);
+    dicke[mm] = p / binom;
+  }
+}
+
 // Im Tr rho (separate, one block).
 template <typename E>
 __global__ void trace_im_kernel(const E* __restrict__ rho, int64_t ld, int64_t N, double* out) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   double part = 0.0;
   for (int64_t s = threadIdx.x; s < N; s += TPB) part += double(rho[s * ld + s].im);
   const double t = block_sum(part, sh);
@@ -640,7 +707,7 @@ __global__ void identity_c128_kernel(c128* __restrict__ X, int64_t ld, int64_t N
 __global__ void grad_trace_kernel(ModelArgs m, const c128* __restrict__ G, int64_t ld, double pr,
                                   double pi, double dt, double* __restrict__ grad_g,
                                   double* __restrict__ grad_delta) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   const int n = m.n;
   const int p = blockIdx.x;
   const int i = p % n;
@@ -834,15 +901,17 @@ int launch_dissipation_c64(const ModelArgs& m, c64* rho, int64_t ld, double dt, 
 }
 
 int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,
-                        double* pdist, hipStream_t s, const int32_t* map) {
-  hipLaunchKernelGGL(readout_kernel<c128>, dim3(1), dim3(TPB), 0, s, m, rho, ld, map, pop, pdist);
+                        double* pdist, hipStream_t s, const int32_t* map, double* pstate) {
+  hipLaunchKernelGGL(readout_kernel<c128>, dim3(1), dim3(TPB), 0, s, m, rho, ld, map, pop, pdist,
+                     pstate);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
 
 int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
-                       double* pdist, hipStream_t s, const int32_t* map) {
-  hipLaunchKernelGGL(readout_kernel<c64>, dim3(1), dim3(TPB), 0, s, m, rho, ld, map, pop, pdist);
+                       double* pdist, hipStream_t s, const int32_t* map, double* pstate) {
+  hipLaunchKernelGGL(readout_kernel<c64>, dim3(1), dim3(TPB), 0, s, m, rho, ld, map, pop, pdist,
+                     pstate);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -865,30 +934,47 @@ int launch_renorm_c64(c64* rho, int64_t ld, int64_t N, double* scratch, hipStrea
   return renorm_impl(rho, ld, N, scratch, s);
 }
 
+// Layout of the partials buffer: 3 per tile pair, the diagonal (N), Im Tr
+// (8 slots), then the Dicke partials (min(n, c) + 1) ceil(2^n / 4) <= N.
 size_t observables_partials_count(int64_t N) {
-  return size_t(3 * npairs_of(N) + N + 8);
+  return size_t(3 * npairs_of(N) + N + 8 + N);
 }
 
 int launch_observables(const ModelArgs& m, const void* rho, int dtype, int64_t ld,
                        double* partials, double* scalars, double* atom_pop,
-                       double* photon_dist, double* exc_dist, hipStream_t s) {
+                       double* photon_dist, double* exc_dist, double* photon_state,
+                       double* dicke, hipStream_t s) {
   const int64_t N = m.N;
   const int64_t np = npairs_of(N);
   double* diag = partials + 3 * np;
   double* tim = diag + N;
+  double* dpart = tim + 8;
+  const int64_t per = int64_t(1) << m.n;
+  const int64_t nblk = (per + TPB / 64 - 1) / (TPB / 64);
+  const int ns = (m.n < m.c ? m.n : m.c) + 1;
   if (dtype == TC_C128) {
     const c128* r = static_cast<const c128*>(rho);
     hipLaunchKernelGGL(obs_pass1<c128>, dim3(unsigned(np)), dim3(TPB), 0, s, r, ld, N, partials, diag);
     hipLaunchKernelGGL(trace_im_kernel<c128>, dim3(1), dim3(TPB), 0, s, r, ld, N, tim);
+    if (dicke)
+      hipLaunchKernelGGL(dicke_pass1<c128>, dim3(unsigned(nblk), unsigned(ns)), dim3(TPB), 0, s,
+                         m.n, r, ld, dpart);
   } else {
     const c64* r = static_cast<const c64*>(rho);
     hipLaunchKernelGGL(obs_pass1<c64>, dim3(unsigned(np)), dim3(TPB), 0, s, r, ld, N, partials, diag);
     hipLaunchKernelGGL(trace_im_kernel<c64>, dim3(1), dim3(TPB), 0, s, r, ld, N, tim);
+    if (dicke)
+      hipLaunchKernelGGL(dicke_pass1<c64>, dim3(unsigned(nblk), unsigned(ns)), dim3(TPB), 0, s,
+                         m.n, r, ld, dpart);
   }
   TC_TRY_HIP(hipGetLastError());
   hipLaunchKernelGGL(obs_pass2, dim3(1), dim3(TPB), 0, s, m, partials, np, diag, tim, scalars,
-                     atom_pop, photon_dist, exc_dist);
+                     atom_pop, photon_dist, exc_dist, photon_state);
   TC_TRY_HIP(hipGetLastError());
+  if (dicke) {
+    hipLaunchKernelGGL(dicke_pass2, dim3(unsigned(ns)), dim3(TPB), 0, s, m.n, dpart, nblk, dicke);
+    TC_TRY_HIP(hipGetLastError());
+  }
   return TC_OK;
 }
 

@@ -29,6 +29,9 @@ struct InstPlan {
   bool rho_converted = false;
   void* X = nullptr; int64_t ldx = 0;
   double* scratch = nullptr;    // [4]: trace, non-finite flag, ...
+  // graph-captured single-instance steps read their record index on the device
+  ReadoutItem* ritem = nullptr;
+  int* counter = nullptr;
   SplitPlanes planes;           // split-BF16 operand planes
   // excitation-sector stepping (opts.sectors): rho and X in the sorted order
   // Each sector's positions are padded to a multiple of the product tile
@@ -79,7 +82,7 @@ int validate_instance(const tc_instance* in, const tc_evolve_opts* o, ModelArgs*
   TC_CHECK_ARG(in->N == m->N, "instance N != (c+1) 2^n");
   TC_CHECK_ARG(in->U != nullptr && in->rho != nullptr, "U / rho is NULL");
   TC_CHECK_ARG(in->ldu >= in->N && in->ldr >= in->N, "leading dimension < N");
-  if (in->pop_out || in->photon_dist_out)
+  if (in->pop_out || in->photon_dist_out || in->photon_state_out)
     TC_CHECK_ARG(o->record_every >= 1, "record_every must be >= 1 when records are requested");
   if (in->checkpoints)
     TC_CHECK_ARG(o->checkpoint_every >= 1, "checkpoint_every must be >= 1 with checkpoints");
@@ -154,6 +157,10 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
   p->m = m;
   p->N = N;
   p->scratch = static_cast<double*>(ar.take(4 * sizeof(double)));
+  if (o.use_graph) {
+    p->ritem = static_cast<ReadoutItem*>(ar.take(sizeof(ReadoutItem)));
+    p->counter = static_cast<int*>(ar.take(sizeof(int)));
+  }
   if (o.sectors) {
     plan_sectors(o, ar, p);
     return;
@@ -185,11 +192,12 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
 }
 
 int readout(const InstPlan& p, const tc_evolve_opts& o, double* pop, double* pdist,
-            hipStream_t s) {
+            double* pstate, hipStream_t s) {
   if (o.gemm_mode == TC_GEMM_F64)
     return launch_readout_c128(p.m, static_cast<const c128*>(p.rho), p.ldr, pop, pdist, s,
-                               p.inv);
-  return launch_readout_c64(p.m, static_cast<const c64*>(p.rho), p.ldr, pop, pdist, s, p.inv);
+                               p.inv, pstate);
+  return launch_readout_c64(p.m, static_cast<const c64*>(p.rho), p.ldr, pop, pdist, s, p.inv,
+                            pstate);
 }
 
 // Sector order: rebuilds the lower block triangle of rho hat from the upper one
@@ -564,24 +572,107 @@ int step(InstPlan& p, const tc_evolve_opts& o, hipStream_t s) {
   return step_mfma(p, o, s);
 }
 
+// The step pattern repeats with period lcm(record_every, renorm_every); a
+// captured chunk is a whole number of periods of about 16 steps.
+int64_t gcd64(int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; }
+
+int64_t graph_chunk(const tc_evolve_opts& o, bool rec) {
+  int64_t L = 1;
+  if (rec && o.record_every > 0) L = o.record_every;
+  if (o.renorm_every > 0) L = L / gcd64(L, o.renorm_every) * o.renorm_every;
+  return L * std::max<int64_t>(1, 16 / L);
+}
+
+// Steps 1..steps through one_step(st, stream).  With graph, the launches of
+// steps 1..chunk are captured once into a hipGraph on a stream of its own
+// (ordered after and before s by events) and replayed steps / chunk times;
+// the remaining steps run eagerly on that stream.  Every launch of a captured
+// step must address the same memory in every period (record indices come from
+// a device counter), and nothing in it may be a memset node.
+template <class StepFn>
+int run_steps(StepFn&& one_step, int64_t steps, int64_t chunk, bool graph, hipStream_t s) {
+  if (!graph) {
+    for (int64_t st = 1; st <= steps; ++st) TC_RETURN_IF(one_step(st, s));
+    return TC_OK;
+  }
+  hipStream_t cs = nullptr;
+  hipEvent_t ev = nullptr;
+  hipGraph_t gr = nullptr;
+  hipGraphExec_t ex = nullptr;
+  TC_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  int rc = TC_OK;
+  auto hip_ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == TC_OK) {
+      set_error(std::string("hipGraph step chunk: ") + what + ": " + hipGetErrorString(e));
+      rc = TC_ERR_HIP;
+    }
+    return e == hipSuccess;
+  };
+  if (hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
+      hip_ok(hipEventRecord(ev, s), "record") && hip_ok(hipStreamWaitEvent(cs, ev, 0), "wait") &&
+      hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) {
+    profile_suspend(true);
+    for (int64_t st = 1; st <= chunk && rc == TC_OK; ++st) rc = one_step(st, cs);
+    profile_suspend(false);
+    const bool ended = hip_ok(hipStreamEndCapture(cs, &gr), "end capture");
+    if (rc == TC_OK && ended && hip_ok(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0), "instantiate")) {
+      const int64_t reps = steps / chunk;
+      for (int64_t r = 0; r < reps && rc == TC_OK; ++r) hip_ok(hipGraphLaunch(ex, cs), "launch");
+      for (int64_t st = reps * chunk + 1; st <= steps && rc == TC_OK; ++st) rc = one_step(st, cs);
+    }
+    hip_ok(hipEventRecord(ev, cs), "record");
+    hip_ok(hipStreamWaitEvent(s, ev, 0), "wait");
+    hip_ok(hipStreamSynchronize(cs), "sync");
+  }
+  if (ex) (void)hipGraphExecDestroy(ex);
+  if (gr) (void)hipGraphDestroy(gr);
+  if (ev) (void)hipEventDestroy(ev);
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
 int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
   TC_RETURN_IF(prepare(p, in, o, s));
-  const int c1 = p.m.c + 1;
-  const bool rec = (in.pop_out || in.photon_dist_out);
-  if (rec) TC_RETURN_IF(readout(p, o, in.pop_out, in.photon_dist_out, s));
+  const int c1 = p.m.c + 1, ns = std::min(p.m.n, p.m.c) + 1;
+  const bool rec = (in.pop_out || in.photon_dist_out || in.photon_state_out);
+  const int64_t chunk = graph_chunk(o, rec);
+  const bool graph = o.use_graph && !in.checkpoints && chunk <= 256 && o.steps >= chunk;
+  const bool c128s = o.gemm_mode == TC_GEMM_F64;
+  if (graph && rec) {
+    // the record index lives on the device, so that a captured chunk replays
+    ReadoutItem ri;
+    ri.rho = p.rho; ri.ld = p.ldr; ri.n = p.m.n; ri.c = p.m.c;
+    ri.pop = in.pop_out; ri.pdist = in.photon_dist_out; ri.pstate = in.photon_state_out;
+    ri.map = p.inv;
+    TC_TRY_HIP(hipMemcpyAsync(p.ritem, &ri, sizeof(ri), hipMemcpyHostToDevice, s));
+    TC_TRY_HIP(hipMemsetAsync(p.counter, 0, sizeof(int), s));
+    TC_TRY_HIP(hipStreamSynchronize(s));   // ri is host memory of this call
+    TC_RETURN_IF(launch_grouped_readout(p.ritem, 1, c128s, p.counter, s));
+    TC_RETURN_IF(launch_advance_counter(p.counter, s));
+  } else if (rec) {
+    TC_RETURN_IF(readout(p, o, in.pop_out, in.photon_dist_out, in.photon_state_out, s));
+  }
   if (in.checkpoints) TC_RETURN_IF(copy_checkpoint(p, in, o, 0, 0.0, s));
-  for (int64_t st = 1; st <= o.steps; ++st) {
-    TC_RETURN_IF(step(p, o, s));
-    TC_RETURN_IF(dissipate(p, o, s));
-    if (o.renorm_every > 0 && st % o.renorm_every == 0) TC_RETURN_IF(renorm(p, o, s));
+  auto one_step = [&](int64_t st, hipStream_t q) -> int {
+    TC_RETURN_IF(step(p, o, q));
+    TC_RETURN_IF(dissipate(p, o, q));
+    if (o.renorm_every > 0 && st % o.renorm_every == 0) TC_RETURN_IF(renorm(p, o, q));
     if (rec && st % o.record_every == 0) {
-      const int64_t r = st / o.record_every;
-      TC_RETURN_IF(readout(p, o, in.pop_out ? in.pop_out + r : nullptr,
-                           in.photon_dist_out ? in.photon_dist_out + r * c1 : nullptr, s));
+      if (graph) {
+        TC_RETURN_IF(launch_grouped_readout(p.ritem, 1, c128s, p.counter, q));
+        TC_RETURN_IF(launch_advance_counter(p.counter, q));
+      } else {
+        const int64_t r = st / o.record_every;
+        TC_RETURN_IF(readout(p, o, in.pop_out ? in.pop_out + r : nullptr,
+                             in.photon_dist_out ? in.photon_dist_out + r * c1 : nullptr,
+                             in.photon_state_out ? in.photon_state_out + r * ns : nullptr, q));
+      }
     }
     if (in.checkpoints && st % o.checkpoint_every == 0)
-      TC_RETURN_IF(copy_checkpoint(p, in, o, st / o.checkpoint_every, double(st) * o.dt, s));
-  }
+      TC_RETURN_IF(copy_checkpoint(p, in, o, st / o.checkpoint_every, double(st) * o.dt, q));
+    return TC_OK;
+  };
+  TC_RETURN_IF(run_steps(one_step, o.steps, chunk, graph, s));
   return finish(p, in, o, s);
 }
 
@@ -636,8 +727,6 @@ int64_t sector_items(const tc_instance* inst, int count, const tc_evolve_opts& o
     t += inst[b].model->n_atoms + inst[b].model->photon_cutoff + 1;
   return t;
 }
-
-int64_t gcd64(int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; }
 
 int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int count,
                    const tc_evolve_opts& o, const BatchBufs& bb, hipStream_t s) {
@@ -709,7 +798,8 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
     ri[b].pop = inst[b].pop_out;
     ri[b].pdist = inst[b].photon_dist_out;
     ri[b].map = sec ? plans[b].inv : nullptr;
-    rec = rec || inst[b].pop_out || inst[b].photon_dist_out;
+    ri[b].pstate = inst[b].photon_state_out;
+    rec = rec || inst[b].pop_out || inst[b].photon_dist_out || inst[b].photon_state_out;
     ckpt = ckpt || inst[b].checkpoints;
   }
   TC_TRY_HIP(hipMemcpyAsync(bb.ritems, ri.data(), ri.size() * sizeof(ReadoutItem),
@@ -746,50 +836,9 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
     return TC_OK;
   };
 
-  // the step pattern repeats with period L = lcm(record_every, renorm_every)
-  int64_t L = 1;
-  if (rec && o.record_every > 0) L = o.record_every;
-  if (o.renorm_every > 0) L = L / gcd64(L, o.renorm_every) * o.renorm_every;
-  const int64_t chunk = L * std::max<int64_t>(1, 16 / L);
+  const int64_t chunk = graph_chunk(o, rec);
   const bool graph = o.use_graph && !ckpt && chunk <= 256 && o.steps >= chunk;
-  if (!graph) {
-    for (int64_t st = 1; st <= o.steps; ++st) TC_RETURN_IF(one_step(st, s));
-  } else {
-    hipStream_t cs = nullptr;
-    hipEvent_t ev = nullptr;
-    hipGraph_t gr = nullptr;
-    hipGraphExec_t ex = nullptr;
-    TC_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    int rc = TC_OK;
-    auto hip_ok = [&](hipError_t e, const char* what) {
-      if (e != hipSuccess && rc == TC_OK) {
-        set_error(std::string("hipGraph step chunk: ") + what + ": " + hipGetErrorString(e));
-        rc = TC_ERR_HIP;
-      }
-      return e == hipSuccess;
-    };
-    if (hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event") &&
-        hip_ok(hipEventRecord(ev, s), "record") && hip_ok(hipStreamWaitEvent(cs, ev, 0), "wait") &&
-        hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) {
-      profile_suspend(true);
-      for (int64_t st = 1; st <= chunk && rc == TC_OK; ++st) rc = one_step(st, cs);
-      profile_suspend(false);
-      const bool ended = hip_ok(hipStreamEndCapture(cs, &gr), "end capture");
-      if (rc == TC_OK && ended && hip_ok(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0), "instantiate")) {
-        const int64_t reps = o.steps / chunk;
-        for (int64_t r = 0; r < reps && rc == TC_OK; ++r) hip_ok(hipGraphLaunch(ex, cs), "launch");
-        for (int64_t st = reps * chunk + 1; st <= o.steps && rc == TC_OK; ++st) rc = one_step(st, cs);
-      }
-      hip_ok(hipEventRecord(ev, cs), "record");
-      hip_ok(hipStreamWaitEvent(s, ev, 0), "wait");
-      hip_ok(hipStreamSynchronize(cs), "sync");
-    }
-    if (ex) (void)hipGraphExecDestroy(ex);
-    if (gr) (void)hipGraphDestroy(gr);
-    if (ev) (void)hipEventDestroy(ev);
-    (void)hipStreamDestroy(cs);
-    TC_RETURN_IF(rc);
-  }
+  TC_RETURN_IF(run_steps(one_step, o.steps, chunk, graph, s));
   for (int b = 0; b < count; ++b) TC_RETURN_IF(finish(plans[b], inst[b], o, s));
   return TC_OK;
 }
@@ -883,7 +932,7 @@ int tc_evolve_sector_workspace_size(const tc_instance* inst, int32_t k, const tc
   TC_CHECK_ARG(inst->N == d, "instance N != d_k of the sector");
   TC_CHECK_ARG(inst->U != nullptr && inst->rho != nullptr, "U / rho is NULL");
   TC_CHECK_ARG(inst->ldu >= d && inst->ldr >= d, "leading dimension < d_k");
-  if (inst->pop_out || inst->photon_dist_out)
+  if (inst->pop_out || inst->photon_dist_out || inst->photon_state_out)
     TC_CHECK_ARG(o->record_every >= 1, "record_every must be >= 1 when records are requested");
   if (inst->checkpoints)
     TC_CHECK_ARG(o->checkpoint_every >= 1, "checkpoint_every must be >= 1 with checkpoints");
@@ -935,7 +984,8 @@ int tc_observables_workspace_size(int64_t N, size_t* bytes) {
 
 int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype, int64_t N, int64_t ldr,
                    double* scalars, double* atom_pop, double* photon_dist, double* exc_dist,
-                   void* ws, size_t ws_bytes, void* stream) {
+                   double* photon_state, double* dicke, void* ws, size_t ws_bytes,
+                   void* stream) {
   clear_error();
   ModelArgs a;
   TC_RETURN_IF(make_model_args(m, &a));
@@ -951,7 +1001,7 @@ int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype, int64_
     return TC_ERR_WORKSPACE;
   }
   return launch_observables(a, rho, rho_dtype, ldr, static_cast<double*>(ws), scalars, atom_pop,
-                            photon_dist, exc_dist, as_stream(stream));
+                            photon_dist, exc_dist, photon_state, dicke, as_stream(stream));
 }
 
 int tc_gemm_workspace_size(int64_t M, int64_t N, int64_t K, int32_t mode, size_t* bytes) {

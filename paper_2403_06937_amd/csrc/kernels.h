@@ -43,16 +43,21 @@ int launch_frame_phase_c64(const ModelArgs& m, c64* rho, int64_t ld, double t, h
 int launch_dissipation_c128(const ModelArgs& m, c128* rho, int64_t ld, double dt, hipStream_t s);
 int launch_dissipation_c64(const ModelArgs& m, c64* rho, int64_t ld, double dt, hipStream_t s);
 
-// Per-step readout of the diagonal: pop[r] = sum_s |l(s)| Re rho_ss and, if
-// pdist != NULL, pdist[r*(c+1) + m] = sum_{photon(s) = m} Re rho_ss.  With a
-// map, basis state s is row and column map[s] of rho (sector-sorted order).
+// Per-step readout of the diagonal: *pop = sum_s |l(s)| Re rho_ss; if
+// pdist != NULL, pdist[m] = sum_{photon(s) = m} Re rho_ss (m = 0..c); if
+// pstate != NULL, pstate[m] = P({m>) of Eq. (13), the sum over the states with
+// m photons and n - m excited atoms (m = 0..min(n, c)).  With a map, basis
+// state s is row and column map[s] of rho (sector-sorted order).
 int launch_readout_c128(const ModelArgs& m, const c128* rho, int64_t ld, double* pop,
-                        double* pdist, hipStream_t s, const int32_t* map = nullptr);
+                        double* pdist, hipStream_t s, const int32_t* map = nullptr,
+                        double* pstate = nullptr);
 int launch_readout_c64(const ModelArgs& m, const c64* rho, int64_t ld, double* pop,
-                       double* pdist, hipStream_t s, const int32_t* map = nullptr);
+                       double* pdist, hipStream_t s, const int32_t* map = nullptr,
+                       double* pstate = nullptr);
 
 // Readout of many instances in one launch (one workgroup each): record index
-// r = *counter; pop[r] and pdist[r*(c+1) + m] as above.  advance_counter adds 1.
+// r = *counter; pop[r], pdist[r*(c+1) + m] and pstate[r*(min(n,c)+1) + m] as
+// above.  advance_counter adds 1.
 struct ReadoutItem {
   const void* rho;
   int64_t ld;
@@ -60,6 +65,7 @@ struct ReadoutItem {
   double* pop;      // may be NULL
   double* pdist;    // may be NULL
   const int32_t* map;   // NULL, or the position of each basis state in rho (sector order)
+  double* pstate;   // may be NULL
 };
 int launch_grouped_readout(const ReadoutItem* items_dev, int count, bool c128_storage,
                            const int* counter, hipStream_t s);
@@ -70,11 +76,12 @@ int launch_advance_counter(int* counter, hipStream_t s);
 int launch_renorm_c128(c128* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s);
 int launch_renorm_c64(c64* rho, int64_t ld, int64_t N, double* scratch, hipStream_t s);
 
-// tc_observables: partials buffer of observables_partials_size() doubles.
+// tc_observables: partials buffer of observables_partials_count(N) doubles.
 size_t observables_partials_count(int64_t N);
 int launch_observables(const ModelArgs& m, const void* rho, int dtype, int64_t ld,
                        double* partials, double* scalars, double* atom_pop,
-                       double* photon_dist, double* exc_dist, hipStream_t s);
+                       double* photon_dist, double* exc_dist, double* photon_state,
+                       double* dicke, hipStream_t s);
 
 // ---- adjoint helpers
 // O = diag(sum_i s_i^+ s_i^-) written densely (zeros off the diagonal).

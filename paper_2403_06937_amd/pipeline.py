@@ -45,23 +45,30 @@ def propagator(model: Model, dt: float, method: int = TC_EXPM_SS_TAYLOR, device=
 def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: float,
            gemm_mode: int = TC_GEMM_F64, frame: int = TC_FRAME_LAB, renorm_every: int = 0,
            record_every: int = 1, checkpoint_every: int = 0, record_photons: bool = False,
-           ws=None, full_product: bool = False, sectors: bool = False):
+           ws=None, full_product: bool = False, sectors: bool = False,
+           record_states: bool = False, use_graph: bool = False):
     """Steps rho (device, complex128 or complex64) in place; returns the records
-    (pop [R], photon distribution [R, c+1] or None, checkpoints or None)."""
+    (pop [R], photon distribution [R, c+1] or None, checkpoints or None), and
+    with record_states also the Eq. (13) records [R, min(n, c)+1] as a fourth."""
     rho_dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
     R = steps // record_every + 1 if record_every else 0
     pop = torch.zeros(R, dtype=torch.float64, device=rho.device) if R else None
     pd = (torch.zeros((R, model.c + 1), dtype=torch.float64, device=rho.device)
           if (R and record_photons) else None)
+    ps = (torch.zeros((R, min(model.n, model.c) + 1), dtype=torch.float64, device=rho.device)
+          if (R and record_states) else None)
     ck = None
     if checkpoint_every:
         ck = torch.empty((steps // checkpoint_every + 1, model.N, model.N), dtype=rho.dtype,
                          device=rho.device)
     opts = make_opts(steps, dt, gemm_mode, rho_dtype, frame, renorm_every,
                      record_every if record_every else 0, checkpoint_every,
-                     full_product=int(full_product), sectors=int(sectors))
-    inst = make_instance(model, U, rho, pop, pd, ck)
+                     use_graph=int(use_graph), full_product=int(full_product),
+                     sectors=int(sectors))
+    inst = make_instance(model, U, rho, pop, pd, ck, ps)
     tc_evolve([inst], opts, ws=ws, device=rho.device)
+    if record_states:
+        return pop, pd, ck, ps
     return pop, pd, ck
 
 
@@ -114,9 +121,13 @@ def observables(model: Model, rho: torch.Tensor) -> dict:
     ap = torch.zeros(model.n, dtype=torch.float64, device=rho.device)
     pd = torch.zeros(model.c + 1, dtype=torch.float64, device=rho.device)
     ed = torch.zeros(model.n + model.c + 1, dtype=torch.float64, device=rho.device)
-    tc_observables(model, rho, s, ap, pd, ed)
+    ns = min(model.n, model.c) + 1
+    ps = torch.zeros(ns, dtype=torch.float64, device=rho.device)
+    dk = torch.zeros(ns, dtype=torch.float64, device=rho.device)
+    tc_observables(model, rho, s, ap, pd, ed, ps, dk)
     v = s.cpu().numpy()
     return {"trace_re": v[0], "trace_im": v[1], "purity": v[2], "herm_err": v[3],
             "excitation_total": v[4], "photon_mean": v[5], "excitation_mean": v[6],
             "nonfinite": v[7], "atom_pop": ap.cpu().numpy(), "photon_dist": pd.cpu().numpy(),
-            "exc_dist": ed.cpu().numpy()}
+            "exc_dist": ed.cpu().numpy(), "photon_state": ps.cpu().numpy(),
+            "dicke": dk.cpu().numpy()}

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_dim():
-    assert tcm.tc_version() == 110
+    assert tcm.tc_version() == 120
     assert tcm.tc_dim(3, 3) == 32
     assert tcm.tc_dim(11, 5) == 12288
     assert tcm.tc_dim(1, 0) == 2

@@ -204,6 +204,12 @@ def test_observables_match_oracle():
     assert np.max(np.abs(got["atom_pop"] - oobs.atom_populations(rho, n, c))) < 1e-14
     assert np.max(np.abs(got["photon_dist"] - oobs.photon_distribution(rho, n, c))) < 1e-14
     assert np.max(np.abs(got["exc_dist"] - oobs.excitation_distribution(rho, n, c))) < 1e-14
+    # both readings of Eq. (13); rho has coherences inside each {m> set, so the
+    # symmetric reading differs from the sector reading
+    ps, dk = oobs.photon_state_probability(rho, n, c), oobs.dicke_probability(rho, n, c)
+    assert np.max(np.abs(ps - dk)) > 1e-3
+    assert np.max(np.abs(got["photon_state"] - ps)) < 1e-14
+    assert np.max(np.abs(got["dicke"] - dk)) < 1e-14
     assert got["nonfinite"] == 0.0
     rho[2, 2] = np.nan
     assert pipeline.observables(m, _dev(rho))["nonfinite"] == 1.0
@@ -218,3 +224,19 @@ def test_observables_complex64_and_ragged():
     r64 = rho.astype(np.complex128)
     assert abs(got["purity"] - oobs.invariants(r64)["purity"]) < 1e-6
     assert np.max(np.abs(got["photon_dist"] - oobs.photon_distribution(r64, n, c))) < 1e-7
+    assert np.max(np.abs(got["photon_state"] - oobs.photon_state_probability(r64, n, c))) < 1e-7
+    assert np.max(np.abs(got["dicke"] - oobs.dicke_probability(r64, n, c))) < 1e-7
+
+
+@pytest.mark.parametrize("n,c", [(1, 3), (5, 2), (6, 6), (11, 5)])
+def test_eq13_readings_shapes(n, c):
+    """Both Eq. (13) readings for c < n, c = n, c > n and the N = 12288 shape
+    (one row of the Dicke pass per atom pattern, 462 states in its largest
+    set) on a random mixed state."""
+    inst = ti.random_model(n, c, 15 + n)
+    m = pipeline.model_of(inst)
+    rho = ti.random_density(m.N, 5, rank=2)
+    got = pipeline.observables(m, _dev(rho))
+    assert got["photon_state"].shape == (min(n, c) + 1,)
+    assert np.max(np.abs(got["photon_state"] - oobs.photon_state_probability(rho, n, c))) < 1e-14
+    assert np.max(np.abs(got["dicke"] - oobs.dicke_probability(rho, n, c))) < 1e-14

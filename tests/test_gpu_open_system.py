@@ -19,8 +19,8 @@ from paper_2403_06937_amd import pipeline  # noqa: E402
 MODES = [
     (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 1e-12),
     (tcm.TC_GEMM_F64, tcm.TC_FRAME_ROTATING, torch.complex128, 1e-12),
-    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 2e-5),
-    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 2e-5),
+    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
 ]
 
 
@@ -73,9 +73,11 @@ def test_against_oracle_split_step(mode, frame, dtype, tol, n, c):
     dt, steps = 0.1, 60
     rho_ref, pop_ref, pd_ref = _oracle(inst, dt, steps)
     rho, pop, pd = _gpu(inst, dt, steps, mode, frame, dtype)
-    assert np.max(np.abs(pop - pop_ref)) < tol * 10
-    assert np.max(np.abs(pd - pd_ref)) < tol * 10
-    assert np.max(np.abs(rho - rho_ref)) < tol
+    e_pop, e_pd = np.max(np.abs(pop - pop_ref)), np.max(np.abs(pd - pd_ref))
+    e_rho = np.max(np.abs(rho - rho_ref))
+    print(f"open n={n} c={c} mode={mode}: max-entry {e_rho:.3e}, population {e_pop:.3e}, "
+          f"photon distribution {e_pd:.3e}", flush=True)
+    assert e_pop <= tol and e_pd <= tol and e_rho <= tol
 
 
 @pytest.mark.parametrize("mode,frame,dtype,tol", MODES)
@@ -83,9 +85,12 @@ def test_invariants(mode, frame, dtype, tol):
     """Trace one, Hermitian and positive semidefinite after 150 lossy steps."""
     inst = _open(4, 3, 70, 0.3, 0.2)
     rho, _, _ = _gpu(inst, 0.2, 150, mode, frame, dtype)
-    assert abs(np.trace(rho) - 1) < tol * 10
-    assert np.max(np.abs(rho - rho.conj().T)) < tol
-    assert np.min(np.linalg.eigvalsh(0.5 * (rho + rho.conj().T))) > -tol * 10
+    e_tr = abs(np.trace(rho) - 1)
+    e_h = np.max(np.abs(rho - rho.conj().T))
+    e_min = np.min(np.linalg.eigvalsh(0.5 * (rho + rho.conj().T)))
+    print(f"open invariants mode={mode}: |Tr - 1| {e_tr:.3e}, herm {e_h:.3e}, "
+          f"min eigenvalue {e_min:.3e}", flush=True)
+    assert e_tr <= tol and e_h <= tol and e_min >= -tol
 
 
 @pytest.mark.parametrize("mode,frame,dtype,tol", [MODES[0], MODES[3]])
@@ -102,8 +107,11 @@ def test_pure_decay_at_full_size(mode, frame, dtype, tol):
     _, pop, pd = _gpu(inst, dt, steps, mode, frame, dtype)
     t = dt * np.arange(steps + 1)
     photons = pd @ np.arange(inst.c + 1)
-    assert np.max(np.abs(photons - 2 * np.exp(-0.08 * t))) < tol * 10
-    assert np.max(np.abs(pop - pop[0] * np.exp(-0.05 * t))) < tol * 10
+    e_ph = np.max(np.abs(photons - 2 * np.exp(-0.08 * t)))
+    e_pop = np.max(np.abs(pop - pop[0] * np.exp(-0.05 * t)))
+    print(f"pure decay N=12288 mode={mode}: photon number {e_ph:.3e}, excitation {e_pop:.3e}",
+          flush=True)
+    assert e_ph <= tol and e_pop <= tol
 
 
 @pytest.mark.parametrize("mode,dtype", [(tcm.TC_GEMM_F32, torch.complex64),

@@ -60,21 +60,32 @@ def test_split_bf16_full_run(setup):
     assert perr <= 1e-5
 
 
-def test_fp32_partial_run(setup):
+def test_fp32_full_run(setup):
+    """All 200 steps in complex FP32 (rotating frame, renormalised every 20
+    steps): every entry of the final rho and every 10th population record
+    within 1e-5 of the FP64 oracle."""
     w, inst, model, U, P, O = setup
-    steps = 40
     rho = torch.from_numpy(inst.rho0()).to("cuda").to(torch.complex64)
-    pipeline.evolve(model, U, rho, steps, w.dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING,
-                    w.renorm_every, 1)
-    err = max_entry_error(rho.cpu().numpy().astype(np.complex128), P.psi(inst.psi0, steps * w.dt))
-    print(f"N=12288 complex-fp32 ({steps} steps): max-entry error {err:.3e}", flush=True)
+    t0 = time.time()
+    pop, _, _ = pipeline.evolve(model, U, rho, w.steps, w.dt, tcm.TC_GEMM_F32,
+                                tcm.TC_FRAME_ROTATING, w.renorm_every, 1)
+    torch.cuda.synchronize()
+    print(f"gpu complex-fp32 {w.steps} steps {time.time() - t0:.2f}s", flush=True)
+    err = max_entry_error(rho.cpu().numpy().astype(np.complex128), P.psi(inst.psi0, w.steps * w.dt))
+    popn = pop.cpu().numpy()
+    perr = max(abs(popn[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * w.dt)) ** 2)))
+               for s in range(0, w.steps + 1, 10))
+    print(f"N=12288 complex-fp32 ({w.steps} steps): max-entry error {err:.3e}, population error "
+          f"{perr:.3e}", flush=True)
     assert err <= 1e-5
+    assert perr <= 1e-5
 
 
-def test_fp64_partial_run(setup):
-    """FP64 over 20 steps (one renormalisation): every entry within 1e-10."""
+def test_fp64_run_100_steps(setup):
+    """FP64 (lab frame) over 100 steps with five renormalisations: every entry
+    of the final rho and every population record within 1e-10."""
     w, inst, model, U, P, O = setup
-    steps = 20
+    steps = 100
     rho = torch.from_numpy(inst.rho0()).to("cuda")
     t0 = time.time()
     pop, _, _ = pipeline.evolve(model, U, rho, steps, w.dt, tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB,
@@ -85,7 +96,8 @@ def test_fp64_partial_run(setup):
     popn = pop.cpu().numpy()
     perr = max(abs(popn[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * w.dt)) ** 2)))
                for s in range(steps + 1))
-    print(f"N=12288 fp64: max-entry error {err:.3e}, population error {perr:.3e}", flush=True)
+    print(f"N=12288 fp64 ({steps} steps): max-entry error {err:.3e}, population error {perr:.3e}",
+          flush=True)
     assert err <= 1e-10 and perr <= 1e-10
 
 
