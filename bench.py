@@ -131,8 +131,9 @@ def bench_n9(tcm, pipeline, ti, steps=100):
 
 def bench_jc3(tcm, pipeline, ti):
     """n = 3, c = 3 (N = 32), FP64, dt = 0.01 x 1000 steps with the excited-atom
-    population recorded every step: launch-bound.  Timed with the launches of
-    every step issued eagerly and as hipGraph-captured chunks."""
+    population recorded every step: launch-bound.  Timed in the LDS-resident
+    kernel (all steps in one launch, the default at this size) and with the
+    launches of every step issued eagerly or as hipGraph-captured chunks."""
     import torch
     w = ti.get("jc3")
     inst = w.instances[0]
@@ -140,14 +141,15 @@ def bench_jc3(tcm, pipeline, ti):
     _, U = pipeline.propagator(m, w.dt)
     rho0 = torch.from_numpy(inst.rho0()).to("cuda")
     out = {"workload": w.name, "N": inst.N, "dtype": "f64", "steps": w.steps}
-    for key, graph in (("eager", False), ("graph", True)):
-        pipeline.evolve(m, U, rho0.clone(), 50, w.dt, use_graph=graph)     # warm-up
+    for key, graph, nores in (("resident", False, False), ("eager", False, True),
+                              ("graph", True, True)):
+        pipeline.evolve(m, U, rho0.clone(), 50, w.dt, use_graph=graph, no_resident=nores)
         rho = rho0.clone()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record()
-        pop, _, _ = pipeline.evolve(m, U, rho, w.steps, w.dt, use_graph=graph)
+        pop, _, _ = pipeline.evolve(m, U, rho, w.steps, w.dt, use_graph=graph, no_resident=nores)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -398,7 +400,13 @@ def bench_sectors11(tcm, pipeline, ti, steps=40):
         tcm.tc_profile_enable(False)
         ms = e0.elapsed_time(e1) / steps
         peak = {"fp64": PEAK_F64, "fp32": PEAK_F32, "split": PEAK_BF16}[key]
-        q = 128 if (key == "split" or tcm.tc_autotune_query(mode, N) == 1) else 64
+        # tile edge the sector blocks are padded to: 128 for split-BF16 and for
+        # FP64 blocks above 1024 states, else the autotuner's table
+        from math import comb
+        maxd = max(sum(comb(inst.n, k - m) for m in range(min(k, inst.c) + 1) if k - m <= inst.n)
+                   for k in range(inst.n + inst.c + 1))
+        q = 128 if (key == "split" or (key == "fp64" and maxd > 1024)
+                    or tcm.tc_autotune_query(mode, N) == 1) else 64
         fx = sector_executed_flop_per_step(inst.n, inst.c, q)
         out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
                     "tflops": fl / (ms * 1e-3) / 1e12,

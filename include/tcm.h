@@ -199,6 +199,13 @@ typedef struct {
   int32_t full_product;     /* 0: rho' = X U^dag is Hermitian, so its upper tile
                                triangle is multiplied and mirrored (rho(0) must be
                                Hermitian); 1: every tile of both products        */
+  int32_t no_resident;      /* 0: a single instance with N <= 48 (FP64 products) or
+                               N <= 64 (complex FP32), stepped densely with no
+                               checkpoints and no Lindblad term, runs every step
+                               in one launch of one workgroup that keeps U (or D),
+                               rho and X in LDS (the per-step launches of such a
+                               run would cost more than its arithmetic); same
+                               results to rounding.  1: never                      */
   int32_t sectors;          /* 0: dense N x N products.  1: excitation-sector
                                block stepping, in every gemm_mode (count > 1:
                                the blocks of all instances in one grouped

@@ -90,7 +90,7 @@ class tc_evolve_opts(ctypes.Structure):
                 ("frame", ctypes.c_int32), ("renorm_every", ctypes.c_int32),
                 ("record_every", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("full_product", ctypes.c_int32),
-                ("sectors", ctypes.c_int32)]
+                ("no_resident", ctypes.c_int32), ("sectors", ctypes.c_int32)]
 
 
 _lib = None
@@ -242,10 +242,10 @@ def tc_expm(H, dt: float, lam_lo: float, lam_hi: float, U, method: int = TC_EXPM
 
 def make_opts(steps, dt, gemm_mode=TC_GEMM_F64, rho_dtype=TC_C128, frame=TC_FRAME_LAB,
               renorm_every=0, record_every=1, checkpoint_every=0, use_graph=0, full_product=0,
-              sectors=0):
+              sectors=0, no_resident=0):
     return tc_evolve_opts(int(steps), float(dt), gemm_mode, rho_dtype, frame, renorm_every,
                           record_every, checkpoint_every, use_graph, int(full_product),
-                          int(sectors))
+                          int(no_resident), int(sectors))
 
 
 def make_instance(model: Model, U, rho, pop_out=None, photon_dist_out=None, checkpoints=None,

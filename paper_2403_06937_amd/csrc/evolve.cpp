@@ -41,6 +41,7 @@ struct InstPlan {
   int in_sector = -1;
   bool sectors = false;
   int64_t Np = 0;                    // padded dimension of the sorted order
+  int svar = 2;                      // tile shape of the grouped block products (1: 128, 2: 64)
   std::vector<int64_t> sdim;         // d_k: states of sector k
   std::vector<int64_t> spo, spd;     // sector k: padded positions [spo[k], spo[k] + spd[k])
   std::vector<size_t> boff;          // element offset of block k (spd[k]^2) in blocks
@@ -111,10 +112,15 @@ void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
   // pad to the edge of the grouped product's tile (128 or 64; the split
   // product's tile is 128)
   const bool split = o.gemm_mode == TC_GEMM_SPLIT_BF16;
-  const int64_t q = split ? SPLIT_BM : (tile_variant_for(N, f64) == 1 ? 128 : 64);
   p->sectors = true;
   std::vector<int64_t> off;
   sector_sizes(p->m.n, p->m.c, p->sdim, off);
+  // FP64 blocks above 1024 states take 128 x 128 tiles (0.81 of the FP64 peak
+  // on the padded work at N = 12288 against 0.75 with 64 x 64, for slightly
+  // less time despite the extra padding); otherwise the autotuner's table
+  const int64_t maxd = *std::max_element(p->sdim.begin(), p->sdim.end());
+  p->svar = (f64 && maxd > 1024) ? 1 : tile_variant_for(N, f64);
+  const int64_t q = split ? SPLIT_BM : (p->svar == 1 ? 128 : 64);
   const int ns = int(p->sdim.size());
   p->spo.assign(ns, 0);
   p->spd.assign(ns, 0);
@@ -467,7 +473,7 @@ int prepare_sectors(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o,
     d2.push_back(g2);
   }
   if (!build) return TC_OK;
-  const int v = tile_variant_for(N, f64);
+  const int v = p.svar;
   TC_RETURN_IF(grouped_build(d1, f64, v, p.items, &p.g1, s));
   TC_RETURN_IF(grouped_build(d2, f64, v, p.items + grouped_bytes(ns), &p.g2, s));
   p.g1.persistent = p.g2.persistent = false;     // whole tiles: one workgroup each
@@ -631,7 +637,34 @@ int run_steps(StepFn&& one_step, int64_t steps, int64_t chunk, bool graph, hipSt
   return rc;
 }
 
+// One small instance stepped densely, without checkpoints or damping, runs
+// in the LDS-resident kernel (one launch for all steps).
+bool use_resident(const InstPlan& p, const tc_instance& in, const tc_evolve_opts& o) {
+  if (o.no_resident || p.sectors || p.in_sector >= 0 || in.checkpoints) return false;
+  if (p.m.kappa > 0.0 || p.m.gamma > 0.0) return false;
+  if (o.gemm_mode == TC_GEMM_F64) return p.N <= RESIDENT_MAX_N_C128;
+  if (o.gemm_mode == TC_GEMM_F32) return p.N <= RESIDENT_MAX_N_C64;
+  return false;
+}
+
+int evolve_resident(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  TC_RETURN_IF(prepare(p, in, o, s));
+  ResidentArgs a;
+  a.op = p.op; a.ldop = p.ldop;
+  a.rho = p.rho; a.ldr = p.ldr;
+  a.rot = o.frame == TC_FRAME_ROTATING;
+  a.steps = o.steps;
+  a.renorm_every = o.renorm_every;
+  a.record_every = o.record_every;
+  a.pop = in.pop_out; a.pdist = in.photon_dist_out; a.pstate = in.photon_state_out;
+  a.scratch = p.scratch;
+  TC_RETURN_IF(o.gemm_mode == TC_GEMM_F64 ? launch_resident_c128(p.m, a, s)
+                                          : launch_resident_c64(p.m, a, s));
+  return finish(p, in, o, s);
+}
+
 int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipStream_t s) {
+  if (use_resident(p, in, o)) return evolve_resident(p, in, o, s);
   TC_RETURN_IF(prepare(p, in, o, s));
   const int c1 = p.m.c + 1, ns = std::min(p.m.n, p.m.c) + 1;
   const bool rec = (in.pop_out || in.photon_dist_out || in.photon_state_out);
@@ -743,7 +776,7 @@ int evolve_batched(std::vector<InstPlan>& plans, const tc_instance* inst, int co
   std::vector<GemmDesc> d1[3][2], d2[3][2];
   std::vector<SplitProduct> sp1, sp2;
   for (int b = 0; b < count; ++b) {
-    const int v = tile_variant_for(plans[b].N, f64);
+    const int v = sec ? plans[b].svar : tile_variant_for(plans[b].N, f64);
     if (sec && split) {
       sp1.insert(sp1.end(), plans[b].ssd1.begin(), plans[b].ssd1.end());
       sp2.insert(sp2.end(), plans[b].ssd2.begin(), plans[b].ssd2.end());

@@ -169,6 +169,29 @@ int launch_block_diag_c64(const BlockTable& t, const c64* blocks, int64_t Np, c6
 int launch_scale_vec_c128(c128* x, int64_t count, double a, hipStream_t s);
 int launch_accumulate_vec_c64(const c64* t, c128* m, int64_t count, hipStream_t s);
 
+// ---- LDS-resident stepping of one small instance (resident.hip)
+// All steps in one launch of one workgroup, op, rho and X held in LDS:
+// X = op R (+ R if rot), R' = X op^dag (+ X if rot) per step, renormalisation
+// in FP64 every renorm_every steps (scratch[0] = last trace, scratch[1] = 1
+// once a trace is non-finite or non-positive), records of the diagonal
+// every record_every steps (record 0 = the initial state), rho written back at
+// the end.  The master storage is c128 (N <= 48) or c64 (N <= 64).
+constexpr int RESIDENT_MAX_N_C128 = 48;
+constexpr int RESIDENT_MAX_N_C64 = 64;
+struct ResidentArgs {
+  const void* op; int64_t ldop;   // U (lab) or D = U~ - I (rotating), master precision
+  void* rho; int64_t ldr;         // master state, in/out
+  int rot;
+  int64_t steps;
+  int renorm_every, record_every;
+  double* pop;                    // [steps/record_every + 1] or NULL
+  double* pdist;                  // [..][c + 1] or NULL
+  double* pstate;                 // [..][min(n, c) + 1] or NULL
+  double* scratch;                // [2]
+};
+int launch_resident_c128(const ModelArgs& m, const ResidentArgs& a, hipStream_t s);
+int launch_resident_c64(const ModelArgs& m, const ResidentArgs& a, hipStream_t s);
+
 // bfloat16 hi/lo split of binary32 values.
 int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo, hipStream_t s);
 

@@ -46,7 +46,7 @@ def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: flo
            gemm_mode: int = TC_GEMM_F64, frame: int = TC_FRAME_LAB, renorm_every: int = 0,
            record_every: int = 1, checkpoint_every: int = 0, record_photons: bool = False,
            ws=None, full_product: bool = False, sectors: bool = False,
-           record_states: bool = False, use_graph: bool = False):
+           record_states: bool = False, use_graph: bool = False, no_resident: bool = False):
     """Steps rho (device, complex128 or complex64) in place; returns the records
     (pop [R], photon distribution [R, c+1] or None, checkpoints or None), and
     with record_states also the Eq. (13) records [R, min(n, c)+1] as a fourth."""
@@ -64,7 +64,7 @@ def evolve(model: Model, U: torch.Tensor, rho: torch.Tensor, steps: int, dt: flo
     opts = make_opts(steps, dt, gemm_mode, rho_dtype, frame, renorm_every,
                      record_every if record_every else 0, checkpoint_every,
                      use_graph=int(use_graph), full_product=int(full_product),
-                     sectors=int(sectors))
+                     sectors=int(sectors), no_resident=int(no_resident))
     inst = make_instance(model, U, rho, pop, pd, ck, ps)
     tc_evolve([inst], opts, ws=ws, device=rho.device)
     if record_states:

