@@ -7,7 +7,7 @@
 // is bound by launch latency.  Here the launch is paid once per run and each
 // step costs the products' arithmetic and two workgroup barriers.
 //
-// Per step, for every output (i, j) (one thread per output, strided):
+// Per step, for every output (i, j) (2 x 2 blocks of outputs per thread):
 //   X[i][j]  = sum_k op[i][k] R[k][j]        (+ R[i][j] in the rotating frame)
 //   R'[i][j] = sum_k X[i][k] conj(op[j][k])  (+ X[i][j] in the rotating frame)
 // i.e. X = op R, R' = X op^dag: op = U in the lab frame, D = U~ - I in the
@@ -15,14 +15,19 @@
 // fused multiply-adds in the storage precision.  Renormalisation (every
 // renorm_every steps) is Hermitisation and division by Re Tr R in FP64, and
 // the records (excited-atom population, photon-number distribution, P({m>)
-// of Eq. (13)) are read from the diagonal in FP64 by one thread in basis
-// order.
+// of Eq. (13)) are read from the diagonal in FP64 by one wavefront.
 #include "kernels.h"
 
 namespace tcm {
 namespace {
 
 constexpr int RTPB = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
 
 template <typename T, int MAXN>
 __global__ void __launch_bounds__(RTPB) resident_kernel(ModelArgs m, ResidentArgs a) {
@@ -51,13 +56,16 @@ __global__ void __launch_bounds__(RTPB) resident_kernel(ModelArgs m, ResidentArg
   const int ns = (n < c ? n : c) + 1;
   const bool rec = a.pop || a.pdist || a.pstate;
 
-  // records of R's diagonal, written by thread 0 (rows in basis order)
+  // records of R's diagonal, by wave 0: lane l takes the states s = l, l + 64,
+  // ... of each photon block, then each readout is a butterfly sum over the
+  // wave (every lane ends with the same bits, lane 0 writes)
   auto record = [&](int64_t r) {
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
     double pop = 0.0;
     for (int mm = 0; mm <= c; ++mm) {
       double part = 0.0, st = 0.0;
-      for (int l = 0; l < per; ++l) {
+      for (int l = lane; l < per; l += 64) {
         const int s = mm * per + l;
         const double d = double(R[s * LD + s].re);
         const int pc = __popc(unsigned(l));
@@ -65,48 +73,82 @@ __global__ void __launch_bounds__(RTPB) resident_kernel(ModelArgs m, ResidentArg
         pop += double(pc) * d;
         if (pc == n - mm) st += d;
       }
-      if (a.pdist) a.pdist[r * (c + 1) + mm] = part;
-      if (a.pstate && mm < ns) a.pstate[r * ns + mm] = st;
+      if (a.pdist) {
+        part = wave_sum(part);
+        if (lane == 0) a.pdist[r * (c + 1) + mm] = part;
+      }
+      if (a.pstate && mm < ns) {
+        st = wave_sum(st);
+        if (lane == 0) a.pstate[r * ns + mm] = st;
+      }
     }
-    if (a.pop) a.pop[r] = pop;
+    pop = wave_sum(pop);
+    if (a.pop && lane == 0) a.pop[r] = pop;
   };
 
+  // outputs in 2 x 2 blocks (N is even: N = (c + 1) 2^n with n >= 1), so each
+  // k step loads two elements of each operand for four products
+  const int NB = N >> 1, NBB = NB * NB;
   if (rec) record(0);
   for (int64_t step = 1; step <= a.steps; ++step) {
     // X = op R (+ R)
-    for (int idx = threadIdx.x; idx < NN; idx += RTPB) {
-      const int i = idx / N, j = idx - (idx / N) * N;
-      T xr = 0, xi = 0;
+    for (int idx = threadIdx.x; idx < NBB; idx += RTPB) {
+      const int i = 2 * (idx / NB), j = 2 * (idx - (idx / NB) * NB);
+      T xr[2][2] = {{0, 0}, {0, 0}}, xi[2][2] = {{0, 0}, {0, 0}};
       for (int k = 0; k < N; ++k) {
-        const E u = sU[i * LD + k], r = R[k * LD + j];
-        xr = fma(u.re, r.re, xr);
-        xr = fma(-u.im, r.im, xr);
-        xi = fma(u.re, r.im, xi);
-        xi = fma(u.im, r.re, xi);
+        const E u[2] = {sU[i * LD + k], sU[(i + 1) * LD + k]};
+        const E r[2] = {R[k * LD + j], R[k * LD + j + 1]};
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            xr[p][q] = fma(u[p].re, r[q].re, xr[p][q]);
+            xr[p][q] = fma(-u[p].im, r[q].im, xr[p][q]);
+            xi[p][q] = fma(u[p].re, r[q].im, xi[p][q]);
+            xi[p][q] = fma(u[p].im, r[q].re, xi[p][q]);
+          }
       }
-      if (a.rot) {
-        xr += R[i * LD + j].re;
-        xi += R[i * LD + j].im;
-      }
-      X[i * LD + j] = E{xr, xi};
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int o = (i + p) * LD + j + q;
+          if (a.rot) {
+            xr[p][q] += R[o].re;
+            xi[p][q] += R[o].im;
+          }
+          X[o] = E{xr[p][q], xi[p][q]};
+        }
     }
     __syncthreads();
     // R = X op^dag (+ X)
-    for (int idx = threadIdx.x; idx < NN; idx += RTPB) {
-      const int i = idx / N, j = idx - (idx / N) * N;
-      T yr = 0, yi = 0;
+    for (int idx = threadIdx.x; idx < NBB; idx += RTPB) {
+      const int i = 2 * (idx / NB), j = 2 * (idx - (idx / NB) * NB);
+      T yr[2][2] = {{0, 0}, {0, 0}}, yi[2][2] = {{0, 0}, {0, 0}};
       for (int k = 0; k < N; ++k) {
-        const E x = X[i * LD + k], u = sU[j * LD + k];
-        yr = fma(x.re, u.re, yr);
-        yr = fma(x.im, u.im, yr);
-        yi = fma(x.im, u.re, yi);
-        yi = fma(-x.re, u.im, yi);
+        const E x[2] = {X[i * LD + k], X[(i + 1) * LD + k]};
+        const E u[2] = {sU[j * LD + k], sU[(j + 1) * LD + k]};
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            yr[p][q] = fma(x[p].re, u[q].re, yr[p][q]);
+            yr[p][q] = fma(x[p].im, u[q].im, yr[p][q]);
+            yi[p][q] = fma(x[p].im, u[q].re, yi[p][q]);
+            yi[p][q] = fma(-x[p].re, u[q].im, yi[p][q]);
+          }
       }
-      if (a.rot) {
-        yr += X[i * LD + j].re;
-        yi += X[i * LD + j].im;
-      }
-      R[i * LD + j] = E{yr, yi};
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int o = (i + p) * LD + j + q;
+          if (a.rot) {
+            yr[p][q] += X[o].re;
+            yi[p][q] += X[o].im;
+          }
+          R[o] = E{yr[p][q], yi[p][q]};
+        }
     }
     __syncthreads();
     if (a.renorm_every > 0 && step % a.renorm_every == 0) {
@@ -136,7 +178,7 @@ __global__ void __launch_bounds__(RTPB) resident_kernel(ModelArgs m, ResidentArg
         X = t;
       }
     }
-    // thread 0 reads R's diagonal while the others start the next product,
+    // wave 0 reads R's diagonal while the others start the next product,
     // which only reads R; R is next written after the barrier that follows
     if (rec && step % a.record_every == 0) record(step / a.record_every);
   }
