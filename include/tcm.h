@@ -282,6 +282,23 @@ int tc_observables(const tc_model* m, const void* rho, int32_t rho_dtype,
                    double* photon_dist, double* exc_dist, double* photon_state,
                    double* dicke, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * readout and results as tc_observables, bit for bit, with no workspace
+ * argument.  The partial sums live in a 16 MiB device array inside the
+ * library, one per GPU, held until the process ends; its address is looked up
+ * on the first call on each device.  No call allocates or frees device
+ * memory.  Every call on one GPU shares that GPU's array (it needs no
+ * clearing: each pass writes all of its partials before they are read), so
+ * calls that overlap on one GPU, e.g. on two streams, race; calls ordered on
+ * one stream do not.  N beyond tc_observables_noalloc_max_dim (37 120) gives
+ * TC_ERR_UNSUPPORTED before any device work. */
+int tc_observables_noalloc_max_dim(int64_t* N);
+int tc_observables_noalloc(const tc_model* m, const void* rho, int32_t rho_dtype,
+                           int64_t N, int64_t ldr, double* scalars, double* atom_pop,
+                           double* photon_dist, double* exc_dist, double* photon_state,
+                           double* dicke, void* stream);
+
 /* ------------------------------------------------- a9: differentiation */
 
 int tc_evolve_backward_workspace_size(const tc_model* m, int64_t N,

@@ -48,6 +48,7 @@ EXPORTED = [
     "tc_profile_enable", "tc_profile_read", "tc_autotune_workspace_size", "tc_autotune",
     "tc_autotune_query", "tc_sector_dim", "tc_sector_states", "tc_sector_spectral_bounds",
     "tc_build_sector_hamiltonian", "tc_evolve_sector_workspace_size", "tc_evolve_sector",
+    "tc_observables_noalloc_max_dim", "tc_observables_noalloc",
 ]
 
 TC_KERNEL_GEMM_F64 = 0
@@ -138,6 +139,9 @@ def lib():
             "tc_build_sector_hamiltonian": [P(tc_model), i32, vp, i64, vp],
             "tc_evolve_sector_workspace_size": [P(tc_instance), i32, P(tc_evolve_opts), P(sz)],
             "tc_evolve_sector": [P(tc_instance), i32, P(tc_evolve_opts), vp, sz, vp],
+            "tc_observables_noalloc_max_dim": [P(i64)],
+            "tc_observables_noalloc": [P(tc_model), vp, i32, i64, i64, vp, vp, vp, vp, vp, vp,
+                                       vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -338,6 +342,24 @@ def tc_observables(model: Model, rho, scalars, atom_pop=None, photon_dist=None, 
                                 _ptr(exc_dist), _ptr(photon_state), _ptr(dicke), _ptr(ws),
                                 ws.numel(), _stream(stream)),
            "tc_observables")
+
+
+def tc_observables_noalloc_max_dim() -> int:
+    N = ctypes.c_int64()
+    _check(lib().tc_observables_noalloc_max_dim(ctypes.byref(N)), "tc_observables_noalloc_max_dim")
+    return N.value
+
+
+def tc_observables_noalloc(model: Model, rho, scalars, atom_pop=None, photon_dist=None,
+                           exc_dist=None, photon_state=None, dicke=None, stream=None):
+    """tc_observables without a workspace (the library's own device array)."""
+    import torch
+    dtype = TC_C128 if rho.dtype == torch.complex128 else TC_C64
+    _check(lib().tc_observables_noalloc(ctypes.byref(model.struct), _ptr(rho), dtype,
+                                        rho.shape[0], rho.stride(0), _ptr(scalars),
+                                        _ptr(atom_pop), _ptr(photon_dist), _ptr(exc_dist),
+                                        _ptr(photon_state), _ptr(dicke), _stream(stream)),
+           "tc_observables_noalloc")
 
 
 def tc_evolve_backward_workspace_size(model: Model, opts) -> int:

@@ -246,3 +246,26 @@ def test_sector_entry_points_host_side():
         tcm.tc_evolve_sector_workspace_size(inst2, 3, tcm.make_opts(10, 0.1))
     assert e.value.code == tcm.TC_ERR_UNSUPPORTED
 
+
+def test_noalloc_observables_rejects_before_device_work():
+    """The allocation-free readout refuses a matrix whose partial sums exceed
+    its device array, and bad arguments, before it touches a device (no GPU
+    needed: the pointers are never dereferenced)."""
+    L = tcm.lib()
+    N = ctypes.c_int64()
+    assert L.tc_observables_noalloc_max_dim(ctypes.byref(N)) == tcm.TC_OK
+    assert N.value == 37120
+    big = tcm.Model(12, 9, [0.01] * 12, [1.0] * 12)          # N = 40960
+    rc = L.tc_observables_noalloc(ctypes.byref(big.struct), 0x1000, tcm.TC_C64, big.N, big.N,
+                                  0x2000, None, None, None, None, None, None)
+    assert rc == tcm.TC_ERR_UNSUPPORTED
+    assert b"use tc_observables" in L.tc_last_error()
+    m = tcm.Model(3, 2, [0.01] * 3, [1.0] * 3)
+    assert L.tc_observables_noalloc(ctypes.byref(m.struct), 0x1000, tcm.TC_C64, m.N, m.N - 1,
+                                    0x2000, None, None, None, None, None,
+                                    None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert L.tc_observables_noalloc(ctypes.byref(m.struct), 0x1000, 9, m.N, m.N, 0x2000, None,
+                                    None, None, None, None, None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert L.tc_observables_noalloc(ctypes.byref(m.struct), 0x1000, tcm.TC_C64, m.N, m.N, None,
+                                    None, None, None, None, None,
+                                    None) == tcm.TC_ERR_INVALID_ARGUMENT
