@@ -216,56 +216,87 @@ __global__ void damp_atoms_kernel(E* __restrict__ rho, int64_t ld, int64_t N, in
 }
 
 // Three atoms per pass (bits b0 < b1 < b2) for the complex FP32 state, in
-// FP32 arithmetic (the 8 x 8 block of 64 complex values stays in registers;
-// in FP64 it would not fit): the same channel as above applied for each of
-// the three bits in turn, so a state of n atoms takes ceil(n / 3) passes
-// over the matrix instead of ceil(n / 2).
+// FP32 arithmetic: the same channel as above for each of the three bits, so a
+// state of n atoms takes ceil(n / 3) passes over the matrix instead of
+// ceil(n / 2).  The 8 x 8 block of one row and column triple is shared by two
+// neighbouring lanes: lane h of the pair holds its rows u with u's bit 2
+// (atom b2) equal to h, 32 complex values, so the kernel fits three waves per
+// SIMD (one lane holding all 64 values needed more than 256 registers and ran
+// one wave per SIMD at half of HBM bandwidth).  The channels of different
+// atoms commute, so the b2 channel goes first: its only coupling between the
+// halves, x[u][v] += p x[u|4][v|4] for u, v with bit 2 clear, takes the
+// partner's 16 values x[u|4][v|4] by a cross-lane exchange before either lane
+// changes them; the b0 and b1 channels then act inside each half.
 __global__ void __launch_bounds__(TPB)
 damp_atoms3_c64_kernel(c64* __restrict__ rho, int64_t ld, int64_t N, int b0, int b1, int b2,
                        float p, float f) {
-  constexpr int B = 8;
   const int64_t R = N >> 3;
-  const int64_t qs = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  if (qs >= R) return;
+  const int64_t tid = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  const int64_t qs = tid >> 1;
+  const int h = int(tid & 1);
+  if (qs >= R) return;                       // both lanes of a pair leave together
   const int64_t s0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qs, b0), b1), b2);
   const int64_t e0 = int64_t(1) << b0, e1 = int64_t(1) << b1, e2 = int64_t(1) << b2;
   const float q1 = 1.f - p;
   for (int64_t qr = blockIdx.y; qr < R; qr += gridDim.y) {
-    const int64_t r0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qr, b0), b1), b2);
-    float xr[B][B], xi[B][B];
+    const int64_t r0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qr, b0), b1), b2) +
+                       (h ? e2 : 0);
+    float xr[4][8], xi[4][8];                // rows u = 4 h + uu, all 8 columns
 #pragma unroll
-    for (int u = 0; u < B; ++u)
+    for (int uu = 0; uu < 4; ++uu)
 #pragma unroll
-      for (int v = 0; v < B; ++v) {
-        const int64_t r = r0 + ((u & 1) ? e0 : 0) + ((u & 2) ? e1 : 0) + ((u & 4) ? e2 : 0);
+      for (int v = 0; v < 8; ++v) {
+        const int64_t r = r0 + ((uu & 1) ? e0 : 0) + ((uu & 2) ? e1 : 0);
         const int64_t c = s0 + ((v & 1) ? e0 : 0) + ((v & 2) ? e1 : 0) + ((v & 4) ? e2 : 0);
         const c64 x = rho[r * ld + c];
-        xr[u][v] = x.re;
-        xi[u][v] = x.im;
+        xr[uu][v] = x.re;
+        xi[uu][v] = x.im;
       }
+    // atom b2: lane 0 gains p x[u|4][v|4] (the partner's columns 4..7), then
+    // scales its columns 4..7 by f; lane 1 scales columns 0..3 by f and 4..7
+    // by 1 - p
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int uu = 0; uu < 4; ++uu)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float pr = __shfl_xor(xr[uu][v + 4], 1, 64);
+        const float pi = __shfl_xor(xi[uu][v + 4], 1, 64);
+        if (h == 0) {
+          xr[uu][v] += p * pr;
+          xi[uu][v] += p * pi;
+          xr[uu][v + 4] *= f;
+          xi[uu][v + 4] *= f;
+        } else {
+          xr[uu][v] *= f;
+          xi[uu][v] *= f;
+          xr[uu][v + 4] *= q1;
+          xi[uu][v + 4] *= q1;
+        }
+      }
+    // atoms b0, b1 inside the half (row bits 0, 1 of uu; column bits 0, 1 of v)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
       const int bit = 1 << k;
 #pragma unroll
-      for (int u = 0; u < B; ++u)
+      for (int uu = 0; uu < 4; ++uu)
 #pragma unroll
-        for (int v = 0; v < B; ++v) {
-          if ((u & bit) || (v & bit)) continue;
-          const int u1 = u | bit, v1 = v | bit;
-          xr[u][v] += p * xr[u1][v1];
-          xi[u][v] += p * xi[u1][v1];
-          xr[u][v1] *= f; xi[u][v1] *= f;
+        for (int v = 0; v < 8; ++v) {
+          if ((uu & bit) || (v & bit)) continue;
+          const int u1 = uu | bit, v1 = v | bit;
+          xr[uu][v] += p * xr[u1][v1];
+          xi[uu][v] += p * xi[u1][v1];
+          xr[uu][v1] *= f; xi[uu][v1] *= f;
           xr[u1][v] *= f; xi[u1][v] *= f;
           xr[u1][v1] *= q1; xi[u1][v1] *= q1;
         }
     }
 #pragma unroll
-    for (int u = 0; u < B; ++u)
+    for (int uu = 0; uu < 4; ++uu)
 #pragma unroll
-      for (int v = 0; v < B; ++v) {
-        const int64_t r = r0 + ((u & 1) ? e0 : 0) + ((u & 2) ? e1 : 0) + ((u & 4) ? e2 : 0);
+      for (int v = 0; v < 8; ++v) {
+        const int64_t r = r0 + ((uu & 1) ? e0 : 0) + ((uu & 2) ? e1 : 0);
         const int64_t c = s0 + ((v & 1) ? e0 : 0) + ((v & 2) ? e1 : 0) + ((v & 4) ? e2 : 0);
-        rho[r * ld + c] = c64{xr[u][v], xi[u][v]};
+        rho[r * ld + c] = c64{xr[uu][v], xi[uu][v]};
       }
   }
 }
@@ -858,9 +889,9 @@ int launch_dissipation_t(const ModelArgs& m, E* rho, int64_t ld, double dt, hipS
     int b = 0;
     if constexpr (std::is_same<E, c64>::value) {
       for (; b + 3 <= m.n; b += 3) {
-        const int64_t R = m.N >> 3;
-        hipLaunchKernelGGL(damp_atoms3_c64_kernel, grid2(R, R), dim3(TPB), 0, s, rho, ld, m.N, b,
-                           b + 1, b + 2, float(p), float(f));
+        const int64_t R = m.N >> 3;            // two lanes per 8 x 8 block
+        hipLaunchKernelGGL(damp_atoms3_c64_kernel, grid2(2 * R, R), dim3(TPB), 0, s, rho, ld,
+                           m.N, b, b + 1, b + 2, float(p), float(f));
         TC_TRY_HIP(hipGetLastError());
       }
     }

@@ -92,9 +92,18 @@ __device__ __forceinline__ uint16_t rne_bf16(float x) {
   const uint32_t up = (rem > 0x8000u) || (rem == 0x8000u && (upper & 1u));
   return uint16_t(upper + up);
 }
+// hi = RNE_bf16(x), lo = RNE_bf16(x - hi) by the hardware conversion
+// (v_cvt_pk_bf16_f32, round to nearest even), which gives rne_bf16's bits for
+// every non-NaN binary32 input (checked exhaustively on gfx950 over all 2^32
+// patterns; a NaN stays a NaN); x - hi is exact in binary32.  One instruction
+// per conversion instead of rne_bf16's integer sequence, which made the split
+// of the result a fifth of the epilogue's instructions.
+__device__ __forceinline__ uint16_t cvt_bf16(float x) {
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
+}
 __device__ __forceinline__ void split2(float x, uint16_t& h, uint16_t& l) {
-  h = rne_bf16(x);
-  l = rne_bf16(x - __uint_as_float(uint32_t(h) << 16));
+  h = cvt_bf16(x);
+  l = cvt_bf16(x - __uint_as_float(uint32_t(h) << 16));
 }
 
 __device__ __forceinline__ f4 mma(const u4& a, const u4& b, f4 c) {
