@@ -258,7 +258,10 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
 
   // Ragged tiles (CHECKED): every lane loads from an address clamped into the
   // operand and zeroes the value if its (row, k) lies outside, so the loads
-  // stay unconditional (no exec-mask branches around them).
+  // stay unconditional (no exec-mask branches around them).  The loads land in
+  // ra / rb untouched; the conjugation and the zeroing are applied when the
+  // registers go to LDS, a K tile later, so that nothing waits for a global
+  // load in the iteration that issues it.
   const E* __restrict__ A0 = static_cast<const E*>(p.A);
   const E* __restrict__ B0 = static_cast<const E*>(p.B);
   auto load_tiles = [&](int64_t kt) {
@@ -270,10 +273,9 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
       if constexpr (CHECKED) {
         const int64_t m = m0 + ma + j * dma, k = k0 + ka + j * dka;
         const int64_t mc = m < M ? m : M - 1, kc = k < K ? k : K - 1;
-        const E v = gload(A0 + (AK ? kc * lda + mc : mc * lda + kc));
-        ra[j] = (m < M && k < K) ? elem<T, CPLX>::cj(v, cja) : elem<T, CPLX>::zero();
+        ra[j] = gload(A0 + (AK ? kc * lda + mc : mc * lda + kc));
       } else {
-        ra[j] = elem<T, CPLX>::cj(gload(qa + j * sja), cja);
+        ra[j] = gload(qa + j * sja);
       }
     }
 #pragma unroll
@@ -281,28 +283,46 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
       if constexpr (CHECKED) {
         const int64_t nn = n0 + nb + j * dnb, k = k0 + kb + j * dkb;
         const int64_t nc = nn < N ? nn : N - 1, kc = k < K ? k : K - 1;
-        const E v = gload(B0 + (BK ? kc * ldb + nc : nc * ldb + kc));
-        rb[j] = (nn < N && k < K) ? elem<T, CPLX>::cj(v, cjb) : elem<T, CPLX>::zero();
+        rb[j] = gload(B0 + (BK ? kc * ldb + nc : nc * ldb + kc));
       } else {
-        rb[j] = elem<T, CPLX>::cj(gload(qb + j * sjb), cjb);
+        rb[j] = gload(qb + j * sjb);
       }
     }
   };
-  auto store_tiles = [&](int buf) {
+  // registers of K tile kt into LDS buffer buf
+  auto store_tiles = [&](int buf, int64_t kt) {
+    const int64_t k0 = kt * BKT;
 #pragma unroll
-    for (int j = 0; j < A_PT; ++j) sA[buf][ka + j * dka][ma + j * dma] = ra[j];
+    for (int j = 0; j < A_PT; ++j) {
+      E v = elem<T, CPLX>::cj(ra[j], cja);
+      if constexpr (CHECKED) {
+        if (!(m0 + ma + j * dma < M && k0 + ka + j * dka < K)) v = elem<T, CPLX>::zero();
+      }
+      sA[buf][ka + j * dka][ma + j * dma] = v;
+    }
 #pragma unroll
-    for (int j = 0; j < B_PT; ++j) sB[buf][kb + j * dkb][nb + j * dnb] = rb[j];
+    for (int j = 0; j < B_PT; ++j) {
+      E v = elem<T, CPLX>::cj(rb[j], cjb);
+      if constexpr (CHECKED) {
+        if (!(n0 + nb + j * dnb < N && k0 + kb + j * dkb < K)) v = elem<T, CPLX>::zero();
+      }
+      sB[buf][kb + j * dkb][nb + j * dnb] = v;
+    }
   };
 
   // LDS buffer t % 2 holds K tile t.  The registers carry tile t + 1 into the
   // other buffer at the start of iteration t (free since the last barrier)
   // and are refilled with tile t + 2 before the products, so a load has a
   // whole iteration to arrive and the barrier waits for no global load.
+  // Past the last K tile the load and the store repeat the last tile (in
+  // bounds, into a buffer no wave reads again) instead of being skipped: with
+  // no branch around them the loaded registers need no copies at a merge,
+  // which would wait for the loads right after issuing them.
+  const int64_t klast = ktiles - 1;
   if (ktiles > 0) {
     load_tiles(0);
-    store_tiles(0);
-    if (ktiles > 1) load_tiles(1);
+    store_tiles(0, 0);
+    load_tiles(klast < 1 ? klast : 1);
   }
   sync_lds();
 
@@ -310,8 +330,8 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
   const int lcol = lane & 15;   // m / n offset within the 16-wide block
   for (int64_t kt = 0; kt < ktiles; ++kt) {
     const int buf = int(kt & 1);
-    if (kt + 1 < ktiles) store_tiles(buf ^ 1);
-    if (kt + 2 < ktiles) load_tiles(kt + 2);
+    store_tiles(buf ^ 1, kt + 1 < klast ? kt + 1 : klast);
+    load_tiles(kt + 2 < klast ? kt + 2 : klast);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k4 = 0; k4 < BKT / 4; ++k4) {
