@@ -214,6 +214,27 @@ __device__ __forceinline__ void tile_coords(int pid, int tiles_m, int tiles_n, i
   tn = in_group / gsize;
 }
 
+// beta's operand for one wave's WM x WN blocks of 16 x 16 outputs, loaded all
+// at once before any of it is used: every lane loads from an address clamped
+// into the matrix (the value is discarded outside it), so the loads need no
+// branch and the wave waits for them once instead of once per element.
+template <int WM, int WN>
+__device__ __forceinline__ void load_cin(const SplitParams& p, int64_t r0, int64_t c0,
+                                         c64 (&cin)[WM][WN][4]) {
+  const int lr = threadIdx.x & 15, lc = (threadIdx.x >> 4) & 3;
+  const int64_t sr = p.cin_trans ? 1 : p.ldcin, sc = p.cin_trans ? p.ldcin : 1;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = min(r0 + i * 16 + 4 * lc + r, p.M - 1);
+        const int64_t col = min(c0 + j * 16 + lr, p.N - 1);
+        cin[i][j][r] = gld_c64(p.Cin + row * sr + col * sc);
+      }
+}
+
 // Epilogue of one wave's WM x WN blocks of 16 x 16 outputs whose first output
 // is (r0, c0): alpha * acc + beta * Cin in FP32, then any of the FP32 result
 // and its hi/lo planes (row-major or transposed).  mirror: the tile lies above
@@ -225,6 +246,8 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
                                                int64_t c0, bool mirror) {
   const bool use_beta = p.Cin != nullptr && (p.br != 0.f || p.bi != 0.f);
   const int lr = threadIdx.x & 15, lc = (threadIdx.x >> 4) & 3;
+  c64 cin[WM][WN][4];
+  if (use_beta) load_cin<WM, WN>(p, r0, c0, cin);
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -239,8 +262,8 @@ __device__ __forceinline__ void split_epilogue(const SplitParams& p, const f4 (&
         float yr = p.ar * xr - p.ai * xi;
         float yi = p.ar * xi + p.ai * xr;
         const bool inb = row < p.M && col < p.N;
-        if (use_beta && inb) {
-          const c64 c = gld_c64(p.Cin + (p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col));
+        if (use_beta) {
+          const c64 c = cin[i][j][r];
           yr += p.br * c.re - p.bi * c.im;
           yi += p.br * c.im + p.bi * c.re;
         }
@@ -311,6 +334,8 @@ __device__ __forceinline__ void split_epilogue_staged(const SplitParams& p, f4 (
   const u4 sgn4 = u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
 
   // alpha acc + beta Cin, kept in acc; the FP32 result row-major from registers
+  c64 cin[WM][WN][4];
+  if (use_beta) load_cin<WM, WN>(p, r0, c0, cin);
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -324,8 +349,8 @@ __device__ __forceinline__ void split_epilogue_staged(const SplitParams& p, f4 (
         float yr = p.ar * xr - p.ai * xi;
         float yi = p.ar * xi + p.ai * xr;
         const bool inb = row < p.M && col < p.N;
-        if (use_beta && inb) {
-          const c64 c = gld_c64(p.Cin + (p.cin_trans ? col * p.ldcin + row : row * p.ldcin + col));
+        if (use_beta) {
+          const c64 c = cin[i][j][r];
           yr += p.br * c.re - p.bi * c.im;
           yi += p.br * c.im + p.bi * c.re;
         }

@@ -365,15 +365,35 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
   const T ar = T(p.alpha_re), ai = T(p.alpha_im), br = T(p.beta_re), bi = T(p.beta_im);
   const T gam = T(p.gamma);
   const bool use_beta = (Cin != nullptr) && (p.beta_re != 0.0 || p.beta_im != 0.0);
+  // FP64 MFMA output r of lane l is row l/16 + 4r; FP32 is row 4(l/16) + r
+  auto out_row = [&](int i, int r) -> int64_t {
+    return m0 + (wm * WM + i) * 16 + (sizeof(T) == 8 ? lrow + 4 * r : 4 * lrow + r);
+  };
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+  for (int i = 0; i < WM; ++i) {
+    // beta's operand for this row of blocks, loaded before any of it is used
+    // (addresses clamped into the matrix, so no branch): one wait per row of
+    // blocks instead of one per element
+    E cin[WN][4];
+    if (use_beta) {
+      const int64_t sr = citr ? 1 : ldcin, sc = citr ? ldcin : 1;
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t row = out_row(i, r), col = n0 + (wn * WN + j) * 16 + lcol;
+          if constexpr (CHECKED) {
+            row = row < M ? row : M - 1;
+            col = col < N ? col : N - 1;
+          }
+          cin[j][r] = gload(Cin + row * sr + col * sc);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // FP64 MFMA output r of lane l is row l/16 + 4r; FP32 is row 4(l/16) + r
-        const int64_t row = m0 + (wm * WM + i) * 16 +
-                            (sizeof(T) == 8 ? lrow + 4 * r : 4 * lrow + r);
+        const int64_t row = out_row(i, r);
         const int64_t col = n0 + (wn * WN + j) * 16 + lcol;
         if (CHECKED && (row >= M || col >= N)) continue;
         const int64_t caddr = ctr ? col * ldc + row : row * ldc + col;
@@ -383,14 +403,14 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
           out.re = ar * xr - ai * xi;
           out.im = ar * xi + ai * xr;
           if (use_beta) {
-            const E y = gload(Cin + (citr ? col * ldcin + row : row * ldcin + col));
+            const E y = cin[j][r];
             out.re += br * y.re - bi * y.im;
             out.im += br * y.im + bi * y.re;
           }
           if (row == col) out.re += gam;
         } else {
           out = ar * acc_re[i][j][r];
-          if (use_beta) out += br * gload(Cin + (citr ? col * ldcin + row : row * ldcin + col));
+          if (use_beta) out += br * cin[j][r];
           if (row == col) out += gam;
         }
         gstore(Cg + caddr, out);
@@ -399,6 +419,7 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
           gstore(Cg + (ctr ? row * ldc + col : col * ldc + row), out);
         }
       }
+  }
 }
 
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
