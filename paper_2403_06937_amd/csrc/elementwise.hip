@@ -7,6 +7,8 @@
 // a fixed order (no atomics), so reruns are bitwise identical.
 #include "kernels.h"
 
+#include <algorithm>
+#include <cstdint>
 #include <type_traits>
 #include "ham_entry.h"
 
@@ -215,6 +217,52 @@ __global__ void damp_atoms_kernel(E* __restrict__ rho, int64_t ld, int64_t N, in
   }
 }
 
+// The three channels on one 8 x 8 block held by two neighbouring lanes: lane
+// h has rows u = 4 h + uu (uu = 0..3) and all 8 columns; bit k of a row or
+// column index is the state of atom k of the three.
+__device__ __forceinline__ void damp3_block(float (&xr)[4][8], float (&xi)[4][8], int h, float p,
+                                            float f) {
+  const float q1 = 1.f - p;
+  // atom b2: lane 0 gains p x[u|4][v|4] (the partner's columns 4..7), then
+  // scales its columns 4..7 by f; lane 1 scales columns 0..3 by f and 4..7
+  // by 1 - p
+#pragma unroll
+  for (int uu = 0; uu < 4; ++uu)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float pr = __shfl_xor(xr[uu][v + 4], 1, 64);
+      const float pi = __shfl_xor(xi[uu][v + 4], 1, 64);
+      if (h == 0) {
+        xr[uu][v] += p * pr;
+        xi[uu][v] += p * pi;
+        xr[uu][v + 4] *= f;
+        xi[uu][v + 4] *= f;
+      } else {
+        xr[uu][v] *= f;
+        xi[uu][v] *= f;
+        xr[uu][v + 4] *= q1;
+        xi[uu][v + 4] *= q1;
+      }
+    }
+  // atoms b0, b1 inside the half (row bits 0, 1 of uu; column bits 0, 1 of v)
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int bit = 1 << k;
+#pragma unroll
+    for (int uu = 0; uu < 4; ++uu)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        if ((uu & bit) || (v & bit)) continue;
+        const int u1 = uu | bit, v1 = v | bit;
+        xr[uu][v] += p * xr[u1][v1];
+        xi[uu][v] += p * xi[u1][v1];
+        xr[uu][v1] *= f; xi[uu][v1] *= f;
+        xr[u1][v] *= f; xi[u1][v] *= f;
+        xr[u1][v1] *= q1; xi[u1][v1] *= q1;
+      }
+  }
+}
+
 // Three atoms per pass (bits b0 < b1 < b2) for the complex FP32 state, in
 // FP32 arithmetic: the same channel as above for each of the three bits, so a
 // state of n atoms takes ceil(n / 3) passes over the matrix instead of
@@ -237,7 +285,6 @@ damp_atoms3_c64_kernel(c64* __restrict__ rho, int64_t ld, int64_t N, int b0, int
   if (qs >= R) return;                       // both lanes of a pair leave together
   const int64_t s0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qs, b0), b1), b2);
   const int64_t e0 = int64_t(1) << b0, e1 = int64_t(1) << b1, e2 = int64_t(1) << b2;
-  const float q1 = 1.f - p;
   for (int64_t qr = blockIdx.y; qr < R; qr += gridDim.y) {
     const int64_t r0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(qr, b0), b1), b2) +
                        (h ? e2 : 0);
@@ -252,44 +299,7 @@ damp_atoms3_c64_kernel(c64* __restrict__ rho, int64_t ld, int64_t N, int b0, int
         xr[uu][v] = x.re;
         xi[uu][v] = x.im;
       }
-    // atom b2: lane 0 gains p x[u|4][v|4] (the partner's columns 4..7), then
-    // scales its columns 4..7 by f; lane 1 scales columns 0..3 by f and 4..7
-    // by 1 - p
-#pragma unroll
-    for (int uu = 0; uu < 4; ++uu)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float pr = __shfl_xor(xr[uu][v + 4], 1, 64);
-        const float pi = __shfl_xor(xi[uu][v + 4], 1, 64);
-        if (h == 0) {
-          xr[uu][v] += p * pr;
-          xi[uu][v] += p * pi;
-          xr[uu][v + 4] *= f;
-          xi[uu][v + 4] *= f;
-        } else {
-          xr[uu][v] *= f;
-          xi[uu][v] *= f;
-          xr[uu][v + 4] *= q1;
-          xi[uu][v + 4] *= q1;
-        }
-      }
-    // atoms b0, b1 inside the half (row bits 0, 1 of uu; column bits 0, 1 of v)
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int bit = 1 << k;
-#pragma unroll
-      for (int uu = 0; uu < 4; ++uu)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          if ((uu & bit) || (v & bit)) continue;
-          const int u1 = uu | bit, v1 = v | bit;
-          xr[uu][v] += p * xr[u1][v1];
-          xi[uu][v] += p * xi[u1][v1];
-          xr[uu][v1] *= f; xi[uu][v1] *= f;
-          xr[u1][v] *= f; xi[u1][v] *= f;
-          xr[u1][v1] *= q1; xi[u1][v1] *= q1;
-        }
-    }
+    damp3_block(xr, xi, h, p, f);
 #pragma unroll
     for (int uu = 0; uu < 4; ++uu)
 #pragma unroll
@@ -297,6 +307,83 @@ damp_atoms3_c64_kernel(c64* __restrict__ rho, int64_t ld, int64_t N, int b0, int
         const int64_t r = r0 + ((uu & 1) ? e0 : 0) + ((uu & 2) ? e1 : 0);
         const int64_t c = s0 + ((v & 1) ? e0 : 0) + ((v & 2) ? e1 : 0) + ((v & 4) ? e2 : 0);
         rho[r * ld + c] = c64{xr[uu][v], xi[uu][v]};
+      }
+  }
+}
+
+// The same three-atom pass for atoms b, b + 1, b + 2 with coalesced memory
+// access.  Each 8 x 8 block's columns lie 2^b apart, so a lane pair reading its
+// own block touches a different cache line with almost every load.  Here a
+// workgroup takes one row triple group (the 8 rows r0 + u 2^b) and a window of
+// W consecutive columns (W a multiple of 8 2^b, so the window holds W / 8 whole
+// column groups): it reads the 8 x W values with 16-byte loads that cover
+// contiguous rows, stages them in LDS, applies damp3_block to each block with
+// two lanes per block as above, and writes the window back the same way.  LDS
+// holds column w of a row at w + w / 8 (rows W + W / 8 + 2 long), which keeps
+// the block reads of a wave on distinct banks for every b.
+__device__ __forceinline__ int damp3_pos(int w) { return w + (w >> 3); }
+
+__global__ void __launch_bounds__(512)
+damp_atoms3_lds_c64_kernel(c64* __restrict__ rho, int64_t ld, int64_t N, int b, int W, float p,
+                           float f) {
+  extern __shared__ float2 sx[];
+  const int pitch = W + (W >> 3) + 2;
+  const int nt = W >> 2;                      // two lanes per block, W / 8 blocks
+  const int t = threadIdx.x;
+  const int64_t e = int64_t(1) << b;
+  const int64_t c0 = int64_t(blockIdx.x) * W;
+  // this lane's block and half
+  const int blk = t >> 1, h = t & 1;
+  const int j = blk & int(e - 1), gi = blk >> b;
+  for (int64_t rg = blockIdx.y; rg < (N >> 3); rg += gridDim.y) {
+    const int64_t r0 = insert_zero_bit(insert_zero_bit(insert_zero_bit(rg, b), b + 1), b + 2);
+    // 8 rows x W columns: piece k * nt + t (two complex values) of every row
+    float4 v[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int64_t col = c0 + 2 * (k * nt + t);
+        v[u][k] = *reinterpret_cast<const float4*>(rho + (r0 + u * e) * ld + col);
+      }
+    __syncthreads();                          // the previous group's window is written out
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int w = 2 * (k * nt + t);       // even: w and w + 1 share a group of 8
+        sx[u * pitch + damp3_pos(w)] = make_float2(v[u][k].x, v[u][k].y);
+        sx[u * pitch + damp3_pos(w) + 1] = make_float2(v[u][k].z, v[u][k].w);
+      }
+    __syncthreads();
+    {
+      float xr[4][8], xi[4][8];
+#pragma unroll
+      for (int uu = 0; uu < 4; ++uu)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int w = (gi << (b + 3)) | (c << b) | j;
+          const float2 x = sx[(4 * h + uu) * pitch + damp3_pos(w)];
+          xr[uu][c] = x.x;
+          xi[uu][c] = x.y;
+        }
+      damp3_block(xr, xi, h, p, f);
+#pragma unroll
+      for (int uu = 0; uu < 4; ++uu)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int w = (gi << (b + 3)) | (c << b) | j;
+          sx[(4 * h + uu) * pitch + damp3_pos(w)] = make_float2(xr[uu][c], xi[uu][c]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int w = 2 * (k * nt + t);
+        const float2 a = sx[u * pitch + damp3_pos(w)], c = sx[u * pitch + damp3_pos(w) + 1];
+        *reinterpret_cast<float4*>(rho + (r0 + u * e) * ld + c0 + w) = make_float4(a.x, a.y, c.x, c.y);
       }
   }
 }
@@ -889,9 +976,26 @@ int launch_dissipation_t(const ModelArgs& m, E* rho, int64_t ld, double dt, hipS
     int b = 0;
     if constexpr (std::is_same<E, c64>::value) {
       for (; b + 3 <= m.n; b += 3) {
-        const int64_t R = m.N >> 3;            // two lanes per 8 x 8 block
-        hipLaunchKernelGGL(damp_atoms3_c64_kernel, grid2(2 * R, R), dim3(TPB), 0, s, rho, ld,
-                           m.N, b, b + 1, b + 2, float(p), float(f));
+        // column window of the coalesced pass: 512 columns, or the 2^n of a
+        // photon block if fewer (so it divides N); it must hold whole column
+        // groups of 8 2^b.  Wider groups (b >= 7, whose window would need more
+        // than the default 64 KB of dynamic LDS) and row strides that break
+        // 16-byte alignment take the per-block kernel.
+        const int64_t per = int64_t(1) << m.n;
+        const int64_t W = std::min<int64_t>(512, per);
+        if ((int64_t(8) << b) <= W && ld % 2 == 0 &&
+            (reinterpret_cast<uintptr_t>(rho) & 15) == 0) {
+          const size_t lds = size_t(8) * size_t(W + W / 8 + 2) * sizeof(float2);
+          const int64_t groups = m.N >> 3;
+          hipLaunchKernelGGL(damp_atoms3_lds_c64_kernel,
+                             dim3(unsigned(m.N / W), unsigned(groups < 4096 ? groups : 4096)),
+                             dim3(unsigned(W / 4)), lds, s, rho, ld, m.N, b, int(W), float(p),
+                             float(f));
+        } else {
+          const int64_t R = m.N >> 3;            // two lanes per 8 x 8 block
+          hipLaunchKernelGGL(damp_atoms3_c64_kernel, grid2(2 * R, R), dim3(TPB), 0, s, rho, ld,
+                             m.N, b, b + 1, b + 2, float(p), float(f));
+        }
         TC_TRY_HIP(hipGetLastError());
       }
     }

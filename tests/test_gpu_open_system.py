@@ -116,6 +116,40 @@ def test_pure_decay_at_full_size(mode, frame, dtype, tol):
     assert e_ph <= tol * max(1.0, 2.0) and e_pop <= tol * max(1.0, float(pop[0]))
 
 
+@pytest.mark.parametrize("pad", [0, 1])
+def test_damping_alone_n10_against_oracle(pad):
+    """n = 10, c = 1 (N = 2048), complex FP32, U = I: one step is the damping
+    channels alone (the FP32 products with the identity are exact).  With the
+    row stride N the three-atom passes (atoms 0-2, 3-5, 6-8) take the 512-column
+    coalesced windows; with the odd stride N + 1 the per-block kernel.  Every
+    element against the oracle's Kraus channels applied to the same FP32-rounded
+    state.  Bar: the ten atom channels and the cavity channel each round every
+    entry a few times in FP32 (unit roundoff 6e-8), so 4e-6 of the largest entry."""
+    n, c = 10, 1
+    inst = _open(n, c, 91, 0.03, 0.07)
+    m = pipeline.model_of(inst)
+    N = m.N
+    dt = 0.5
+    rho0 = inst.rho0().astype(np.complex64)
+    U = torch.eye(N, dtype=torch.complex128, device="cuda")
+    buf = torch.zeros((N, N + pad), dtype=torch.complex64, device="cuda")
+    rho = buf[:, :N]
+    rho.copy_(torch.from_numpy(rho0))
+    pipeline.evolve(m, U, rho, 1, dt, tcm.TC_GEMM_F32, tcm.TC_FRAME_LAB, 0, 1)
+    torch.cuda.synchronize()
+    ref = oos.dissipation(rho0.astype(np.complex128), n, c, 0.03, 0.07, dt)
+    got = rho.cpu().numpy().astype(np.complex128)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    change = np.max(np.abs(ref - rho0))
+    print(f"damping alone n=10 stride {N + pad}: max-entry {err:.3e} of {scale:.3e} "
+          f"(largest change {change:.3e})", flush=True)
+    assert change > 0.05 * scale                         # the channels do act
+    assert err <= 4e-6 * scale
+    if pad:
+        assert torch.all(buf[:, N:] == 0)                # the padding column is untouched
+
+
 @pytest.mark.parametrize("mode,dtype", [(tcm.TC_GEMM_F32, torch.complex64),
                                         (tcm.TC_GEMM_F64, torch.complex128)])
 def test_batched_equals_single(mode, dtype):
