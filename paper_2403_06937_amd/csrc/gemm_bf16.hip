@@ -42,6 +42,7 @@
 #include "gemm_bf16.h"
 #include "profile.h"
 
+#include <atomic>
 #include <cstdlib>
 
 namespace tcm {
@@ -498,9 +499,13 @@ __device__ __forceinline__ void sync_lds() {
 typedef u4 SplitLds[2][4][LDS_PLANE];
 #define LDS_AT(buf, q, row, chunk) [buf][q][(row) * 4 + (chunk)]
 
-template <int WGM, int WGN, int WM, int WN, bool PP>
+// PARTIAL: no epilogue; the raw FP32 accumulators go to partial
+// (float4 k of thread t at element 4 (k NT + t), k over the wave's blocks,
+// real then imaginary) and the epilogue is left to a later kernel that adds
+// the partial sums of the K ranges.
+template <int WGM, int WGN, int WM, int WN, bool PP, bool PARTIAL = false>
 __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn, SplitLds& sA,
-                                           SplitLds& sB) {
+                                           SplitLds& sB, float* __restrict__ partial = nullptr) {
   constexpr int NT = 64 * WGM * WGN;
   static_assert(16 * WM * WGM == SPLIT_BM && 16 * WN * WGN == SPLIT_BN, "128 x 128 tile");
   static_assert(SPLIT_BM == SPLIT_BN, "square tile");
@@ -691,6 +696,18 @@ __device__ __forceinline__ void split_tile(const SplitParams& p, int tm, int tn,
     if (kt < ktiles) step(int(kt & 1), false, 0, false, 0);
   }
 
+  if constexpr (PARTIAL) {
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        gst_u4(partial + 4 * ((k++) * NT + tid), __builtin_bit_cast(u4, acc_re[i][j]));
+        gst_u4(partial + 4 * ((k++) * NT + tid), __builtin_bit_cast(u4, acc_im[i][j]));
+      }
+    return;
+  }
+
   if constexpr (WM == 4 && WN == 2) {
     // the lockstep loop ends without a barrier: its last fragment reads may
     // still be in flight in other waves
@@ -713,6 +730,67 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
   else
     tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   split_tile<WGM, WGN, WM, WN, PP>(p, tm, tn, sA, sB);
+}
+
+// The Hermitian product's last round, split over K.  Its 4656 tiles at
+// N = 12288 fill 18 rounds of 256 CUs and leave 48 for a 19th that would hold
+// most CUs idle for a whole tile.  Instead those tiles are cut into S K ranges
+// (one workgroup each, S x 48 <= 256): split_tail_kernel writes each range's
+// FP32 accumulators to a slot of acc, and split_tail_finish_kernel adds a
+// tile's S slots in order (deterministic) and runs the usual epilogue, mirror
+// included.  Positions base .. base + tail - 1 of the triangle's order are
+// the tiles the main launch (grid base) leaves out.
+constexpr int TAIL_SLOTS = 256;                        // slots of acc
+constexpr int TILE_ACC = SPLIT_BM * SPLIT_BN * 2;      // floats per slot (128 KB)
+
+__global__ void __launch_bounds__(512, 1)
+split_tail_kernel(const SplitParams p, int base, int S, int kc, float* __restrict__ acc) {
+  __shared__ SplitLds sA, sB;
+  const int i = blockIdx.x / S, r = blockIdx.x % S;
+  int tm, tn;
+  tri_coords(xcd_linear(base + i, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  const int64_t ktiles = p.Kp / SPLIT_BK;
+  const int64_t k0 = int64_t(r) * kc;
+  SplitParams q = p;
+  q.A = p.A + k0 * 4 * SPLIT_BK;        // K tile k0 of every row (row stride 4 lda unchanged)
+  q.B = p.B + k0 * 4 * SPLIT_BK;
+  q.Kp = min(int64_t(kc), ktiles - k0) * SPLIT_BK;
+  split_tile<2, 4, 4, 2, true, true>(q, tm, tn, sA, sB, acc + size_t(blockIdx.x) * TILE_ACC);
+}
+
+__global__ void __launch_bounds__(512, 1)
+split_tail_finish_kernel(const SplitParams p, int base, int S, const float* __restrict__ acc) {
+  __shared__ SplitLds sA, sB;
+  constexpr int NT = 512, WM = 4, WN = 2, WGN = 4;
+  const int i = blockIdx.x;
+  int tm, tn;
+  tri_coords(xcd_linear(base + i, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  f4 acc_re[WM][WN], acc_im[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      acc_re[a][b] = f4{0, 0, 0, 0};
+      acc_im[a][b] = f4{0, 0, 0, 0};
+    }
+  for (int r = 0; r < S; ++r) {          // K ranges in order
+    const float* src = acc + size_t(i * S + r) * TILE_ACC;
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+      for (int b = 0; b < WN; ++b) {
+        acc_re[a][b] += __builtin_bit_cast(f4, gld_u4(src + 4 * ((k++) * NT + tid)));
+        acc_im[a][b] += __builtin_bit_cast(f4, gld_u4(src + 4 * ((k++) * NT + tid)));
+      }
+  }
+  const int64_t m0 = int64_t(tm) * SPLIT_BM, n0 = int64_t(tn) * SPLIT_BN;
+  u4* stage = (wave < 4 ? &sA[0][0][0] : &sB[0][0][0]) + (wave & 3) * 1024;
+  split_epilogue_staged(p, acc_re, acc_im, m0 + wm * WM * 16, n0 + wn * WN * 16, tm != tn,
+                        stage);
 }
 
 // Many split products in one launch, one workgroup per tile of the
@@ -805,9 +883,30 @@ int split_variant() {
   return v;
 }
 
+// Compute units of the current device (queried once per device).
+int device_cu_count(int* cus) {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  TC_TRY_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && cache[dev].load() > 0) {
+    *cus = cache[dev].load();
+    return TC_OK;
+  }
+  int n = 0;
+  TC_TRY_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+  if (n <= 0) {
+    set_error("the device reports no compute units");
+    return TC_ERR_HIP;
+  }
+  if (dev >= 0 && dev < 64) cache[dev].store(n);
+  *cus = n;
+  return TC_OK;
+}
+
 int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t Kp, float ar,
               float ai, float br, float bi, const c64* Cin, int64_t ldcin, bool cin_trans, c64* Cf,
-              int64_t ldcf, const Planes4* P, bool p_trans, bool herm, hipStream_t s) {
+              int64_t ldcf, const Planes4* P, bool p_trans, bool herm, hipStream_t s,
+              float* tail_acc = nullptr) {
   SplitParams q;
   q.A = A.base; q.lda = A.ld;
   q.B = B.base; q.ldb = B.ld;
@@ -838,6 +937,30 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
     return TC_ERR_INVALID_ARGUMENT;
   }
   ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
+  if (herm && tail_acc && split_variant() == 0) {
+    // a last round of at most a quarter of the CUs after at least 4 full
+    // rounds: its tiles go split over K into up to TAIL_SLOTS workgroups
+    int cus = 0;
+    TC_RETURN_IF(device_cu_count(&cus));
+    const int64_t full = tiles / cus, tail = tiles % cus, kt = Kp / SPLIT_BK;
+    int S = int(std::min<int64_t>(std::min<int64_t>(cus, TAIL_SLOTS) / std::max<int64_t>(tail, 1),
+                                  std::min<int64_t>(8, kt / 8)));
+    if (full >= 4 && tail > 0 && tail * 4 <= cus && S >= 2) {
+      const int64_t kc = (kt + S - 1) / S;
+      S = int((kt + kc - 1) / kc);         // every K range non-empty
+      const int base = int(full * cus);
+      hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, true>), dim3(unsigned(base)), dim3(512),
+                         0, s, q);
+      TC_TRY_HIP(hipGetLastError());
+      hipLaunchKernelGGL(split_tail_kernel, dim3(unsigned(tail * S)), dim3(512), 0, s, q, base, S,
+                         int(kc), tail_acc);
+      TC_TRY_HIP(hipGetLastError());
+      hipLaunchKernelGGL(split_tail_finish_kernel, dim3(unsigned(tail)), dim3(512), 0, s, q, base,
+                         S, static_cast<const float*>(tail_acc));
+      TC_TRY_HIP(hipGetLastError());
+      return TC_OK;
+    }
+  }
   const dim3 grid{unsigned(tiles), 1u, 1u};
   if (split_variant() == 1)
     hipLaunchKernelGGL((split_gemm_kernel<2, 2, 4, 4, false>), grid, dim3(256), 0, s, q);
@@ -919,6 +1042,12 @@ void split_plan(Arena& ar, int64_t N, SplitPlanes* p) {
   p->opB = take_planes(ar, Np, Np);
   p->X = take_planes(ar, Np, Np);
   p->Rt = take_planes(ar, Np, Np);
+  // partial sums for the Hermitian product's last round once its triangle
+  // spans at least 4 rounds of 256 CUs (32 MB)
+  const int64_t t = Np / SPLIT_BM;
+  p->tail_acc = t * (t + 1) / 2 >= 4 * 256
+                    ? static_cast<float*>(ar.take(size_t(TAIL_SLOTS) * TILE_ACC * sizeof(float)))
+                    : nullptr;
 }
 
 int split_operand(const c64* op, int64_t ld, int64_t N, const SplitPlanes& p, hipStream_t s) {
@@ -943,7 +1072,8 @@ int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotat
   // transposed planes of rho for the next step.  rho' is Hermitian, so with
   // herm only its upper tile triangle is multiplied.
   TC_RETURN_IF(run_split(p.X, p.opB, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
-                         rotating ? X : nullptr, ldx, false, rho, ldr, &p.Rt, true, herm, s));
+                         rotating ? X : nullptr, ldx, false, rho, ldr, &p.Rt, true, herm, s,
+                         p.tail_acc));
   return TC_OK;
 }
 
