@@ -33,6 +33,9 @@ struct InstPlan {
   ReadoutItem* ritem = nullptr;
   int* counter = nullptr;
   SplitPlanes planes;           // split-BF16 operand planes
+  // FP64 / FP32: partial sums of the Hermitian product's last round (split
+  // over K), for N whose tile triangle spans at least 4 rounds of 256 CUs
+  void* tail_ws = nullptr; size_t tail_ws_bytes = 0;
   // excitation-sector stepping (opts.sectors): rho and X in the sorted order
   // Each sector's positions are padded to a multiple of the product tile
   // (padding states hold exact zeros), so every block product is whole tiles.
@@ -156,6 +159,16 @@ void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
 }
 
 // Lays out (or sizes, when ar.base == nullptr) the workspace of one instance.
+// Slots for the partial sums of the Hermitian FP64 / FP32 product's last
+// round: 256 tiles of 128 x 128 complex elements of eb bytes (64 MB in FP64),
+// once the tile triangle spans at least 4 rounds of 256 CUs.
+void take_tail_ws(Arena& ar, int64_t N, size_t eb, InstPlan* p) {
+  const int64_t t = (N + 127) / 128;
+  if (t * (t + 1) / 2 < 4 * 256) return;
+  p->tail_ws_bytes = size_t(256) * 128 * 128 * eb;
+  p->tail_ws = ar.take(p->tail_ws_bytes);
+}
+
 void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelArgs& m, Arena& ar,
                    InstPlan* p) {
   const int64_t N = in.N;
@@ -184,6 +197,7 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
       p->op_own = ar.take(NN * 16); p->op = p->op_own; p->ldop = N;
     }
     p->X = ar.take(NN * 16); p->ldx = N;
+    take_tail_ws(ar, N, 16, p);
   } else {
     // FP32 and split-BF16 keep an FP32 master
     if (o.rho_dtype == TC_C64) {
@@ -194,6 +208,7 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
     p->op_own = ar.take(NN * 8); p->op = p->op_own; p->ldop = N;
     p->X = ar.take(NN * 8); p->ldx = N;
     if (o.gemm_mode == TC_GEMM_SPLIT_BF16) split_plan(ar, N, &p->planes);
+    else take_tail_ws(ar, N, 8, p);
   }
 }
 
@@ -750,6 +765,7 @@ void step_descs(const InstPlan& p, const tc_evolve_opts& o, GemmDesc& g1, GemmDe
   g2.C = p.rho; g2.ldc = p.ldr;
   if (rot) { g2.Cin = p.X; g2.ldcin = p.ldx; g2.beta_re = 1.0; }
   g2.herm = o.full_product == 0;
+  g2.tail_ws = p.tail_ws; g2.tail_ws_bytes = p.tail_ws_bytes;
 }
 
 // Sector blocks of all instances of a batch (0 without sectors).

@@ -31,6 +31,7 @@ namespace tcm {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct acc_t;
@@ -188,10 +189,18 @@ struct TileLds {
 // One BM x BN output tile (tm, tn) of the product described by p.  Shared by
 // the one-product kernel and the persistent grouped kernel; the caller must
 // separate two calls in one workgroup by a barrier (the LDS is reused).
+// Modes of gemm_tile: the whole tile; PARTIAL: the K loop only, the raw
+// accumulators stored to part (16-byte chunk c of thread t at chunk c NT + t,
+// over the blocks' real then imaginary accumulators); FINISH: no K loop, the
+// accumulators are the in-order sum of nparts such slots from part, then the
+// epilogue.
+enum TileMode { TILE_FULL = 0, TILE_PARTIAL = 1, TILE_FINISH = 2 };
+
 template <typename T, bool CPLX, bool AK, bool BK, bool CHECKED,
-          int BM, int BN, int BKT, int WM, int WN, int PADB>
+          int BM, int BN, int BKT, int WM, int WN, int PADB, int MODE = TILE_FULL>
 __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool mirror,
-                                          typename elem<T, CPLX>::type* lds) {
+                                          typename elem<T, CPLX>::type* lds,
+                                          void* part = nullptr, int nparts = 0) {
   typedef typename elem<T, CPLX>::type E;
   typedef typename acc_t<T>::type A4;
   constexpr int WGN = BN / (16 * WN);
@@ -310,51 +319,103 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
     }
   };
 
-  // LDS buffer t % 2 holds K tile t.  The registers carry tile t + 1 into the
-  // other buffer at the start of iteration t (free since the last barrier)
-  // and are refilled with tile t + 2 before the products, so a load has a
-  // whole iteration to arrive and the barrier waits for no global load.
-  // Past the last K tile the load and the store repeat the last tile (in
-  // bounds, into a buffer no wave reads again) instead of being skipped: with
-  // no branch around them the loaded registers need no copies at a merge,
-  // which would wait for the loads right after issuing them.
-  const int64_t klast = ktiles - 1;
-  if (ktiles > 0) {
-    load_tiles(0);
-    store_tiles(0, 0);
-    load_tiles(klast < 1 ? klast : 1);
-  }
-  sync_lds();
-
   const int lrow = lane >> 4;   // k offset within the 4-deep slice
   const int lcol = lane & 15;   // m / n offset within the 16-wide block
-  for (int64_t kt = 0; kt < ktiles; ++kt) {
-    const int buf = int(kt & 1);
-    store_tiles(buf ^ 1, kt + 1 < klast ? kt + 1 : klast);
-    load_tiles(kt + 2 < klast ? kt + 2 : klast);
-    __builtin_amdgcn_sched_barrier(0);
+  // the accumulators as 16-byte chunks, in a fixed order over the blocks
+  struct Chunks { u4 c[sizeof(A4) / 16]; };
+  constexpr int NCH = int(sizeof(A4) / 16);
+  if constexpr (MODE == TILE_FINISH) {
+    // one row of blocks at a time, the slots in order inside it, so that only
+    // that row's partial sums are live next to the accumulators
+    constexpr int PER_ROW = (CPLX ? 2 : 1) * WN * NCH;          // chunks per row of blocks
+    const size_t slot = size_t((CPLX ? 2 : 1) * WM * WN * NCH) * NT;
 #pragma unroll
-    for (int k4 = 0; k4 < BKT / 4; ++k4) {
-      E a[WM], b[WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) a[i] = sA[buf][k4 * 4 + lrow][(wm * WM + i) * 16 + lcol];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) b[j] = sB[buf][k4 * 4 + lrow][(wn * WN + j) * 16 + lcol];
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i) {
+#pragma unroll 1
+      for (int r = 0; r < nparts; ++r) {
+        const u4* src = static_cast<const u4*>(part) + size_t(r) * slot + size_t(i) * PER_ROW * NT;
+        int c = 0;
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
+          Chunks a, b;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) a.c[h] = gload(src + size_t(c + h) * NT + tid);
+          c += NCH;
+          acc_re[i][j] += __builtin_bit_cast(A4, a);
           if constexpr (CPLX) {
-            acc_re[i][j] = mma(a[i].re, b[j].re, acc_re[i][j]);
-            acc_re[i][j] = mma_nega(a[i].im, b[j].im, acc_re[i][j]);
-            acc_im[i][j] = mma(a[i].re, b[j].im, acc_im[i][j]);
-            acc_im[i][j] = mma(a[i].im, b[j].re, acc_im[i][j]);
-          } else {
-            acc_re[i][j] = mma(a[i], b[j], acc_re[i][j]);
+#pragma unroll
+            for (int h = 0; h < NCH; ++h) b.c[h] = gload(src + size_t(c + h) * NT + tid);
+            c += NCH;
+            acc_im[i][j] += __builtin_bit_cast(A4, b);
           }
         }
+      }
+    }
+  } else {
+    // LDS buffer t % 2 holds K tile t.  The registers carry tile t + 1 into the
+    // other buffer at the start of iteration t (free since the last barrier)
+    // and are refilled with tile t + 2 before the products, so a load has a
+    // whole iteration to arrive and the barrier waits for no global load.
+    // Past the last K tile the load and the store repeat the last tile (in
+    // bounds, into a buffer no wave reads again) instead of being skipped: with
+    // no branch around them the loaded registers need no copies at a merge,
+    // which would wait for the loads right after issuing them.
+    const int64_t klast = ktiles - 1;
+    if (ktiles > 0) {
+      load_tiles(0);
+      store_tiles(0, 0);
+      load_tiles(klast < 1 ? klast : 1);
     }
     sync_lds();
+
+    for (int64_t kt = 0; kt < ktiles; ++kt) {
+      const int buf = int(kt & 1);
+      store_tiles(buf ^ 1, kt + 1 < klast ? kt + 1 : klast);
+      load_tiles(kt + 2 < klast ? kt + 2 : klast);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k4 = 0; k4 < BKT / 4; ++k4) {
+        E a[WM], b[WN];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) a[i] = sA[buf][k4 * 4 + lrow][(wm * WM + i) * 16 + lcol];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) b[j] = sB[buf][k4 * 4 + lrow][(wn * WN + j) * 16 + lcol];
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            if constexpr (CPLX) {
+              acc_re[i][j] = mma(a[i].re, b[j].re, acc_re[i][j]);
+              acc_re[i][j] = mma_nega(a[i].im, b[j].im, acc_re[i][j]);
+              acc_im[i][j] = mma(a[i].re, b[j].im, acc_im[i][j]);
+              acc_im[i][j] = mma(a[i].im, b[j].re, acc_im[i][j]);
+            } else {
+              acc_re[i][j] = mma(a[i], b[j], acc_re[i][j]);
+            }
+          }
+      }
+      sync_lds();
+    }
+  }
+  if constexpr (MODE == TILE_PARTIAL) {
+    u4* dst = static_cast<u4*>(part);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const Chunks a = __builtin_bit_cast(Chunks, acc_re[i][j]);
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) gstore(dst + size_t(c + h) * NT + tid, a.c[h]);
+        c += NCH;
+        if constexpr (CPLX) {
+          const Chunks b = __builtin_bit_cast(Chunks, acc_im[i][j]);
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) gstore(dst + size_t(c + h) * NT + tid, b.c[h]);
+          c += NCH;
+        }
+      }
+    return;
   }
 
   // Epilogue: C = alpha * acc + beta * Cin + gamma * [m == n]
@@ -435,6 +496,46 @@ gemm_kernel(const Params p) {
     tile_coords(blockIdx.x, p.tiles_m, p.tiles_n, tm, tn);
   gemm_tile<T, CPLX, AK, BK, CHECKED, BM, BN, BKT, WM, WN, PADB>(p, tm, tn, p.herm && tm != tn,
                                                                  lds);
+}
+
+// The Hermitian product's last round split over K, as for the split-BF16
+// product: the main launch runs the triangle's full rounds of one tile per
+// CU, gemm_tail_kernel runs the remaining tiles' S K ranges (kc K tiles each)
+// and stores their accumulators to one slot each of part, and
+// gemm_tail_finish_kernel adds each tile's S slots in order and runs the
+// epilogue (mirror included).  Positions base .. base + tail - 1 of the
+// triangle's order are the tiles the main launch (grid base) leaves out.
+template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
+          int PADB>
+__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
+gemm_tail_kernel(const Params p, int base, int S, int kc, void* part, size_t slot_bytes) {
+  typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
+  typedef typename L::E E;
+  __shared__ E lds[L::elems];
+  const int i = blockIdx.x / S, r = blockIdx.x % S;
+  int tm, tn;
+  tri_coords(xcd_linear(base + i, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  const int64_t k0 = int64_t(r) * kc * BKT;
+  Params q = p;
+  q.A = static_cast<const E*>(p.A) + (AK ? k0 * p.lda : k0);
+  q.B = static_cast<const E*>(p.B) + (BK ? k0 * p.ldb : k0);
+  q.K = min(int64_t(kc) * BKT, p.K - k0);
+  gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB, TILE_PARTIAL>(
+      q, tm, tn, false, lds, static_cast<char*>(part) + size_t(blockIdx.x) * slot_bytes);
+}
+
+template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
+          int PADB>
+__global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
+gemm_tail_finish_kernel(const Params p, int base, int S, const void* part, size_t slot_bytes) {
+  typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
+  __shared__ typename L::E lds[L::elems];
+  int tm, tn;
+  tri_coords(xcd_linear(base + int(blockIdx.x), p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm,
+             tn);
+  gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB, TILE_FINISH>(
+      p, tm, tn, tm != tn, lds,
+      const_cast<char*>(static_cast<const char*>(part)) + size_t(blockIdx.x) * S * slot_bytes, S);
 }
 
 // Persistent grouped products: items[0 .. count) each describe one product
@@ -576,6 +677,8 @@ template <> struct Variants<float, false> {
   typedef Shp<128, 128, 16, 4, 2, 0> V6;
 };
 
+int device_cus();
+
 template <typename T, bool CPLX, bool AK, bool BK, typename S>
 int launch_shape(const GemmDesc& d, hipStream_t s) {
   Params p;
@@ -596,6 +699,36 @@ int launch_shape(const GemmDesc& d, hipStream_t s) {
   const bool exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
   const dim3 grid{unsigned(tiles), 1u, 1u}, block{unsigned(S::NT), 1u, 1u};
   ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
+  if (p.herm && exact && d.tail_ws) {
+    // a last round of at most a quarter of the CUs after at least 4 full
+    // rounds: its tiles go split over K, one workgroup and slot per range
+    const int cus = device_cus();
+    const int64_t full = tiles / cus, tail = tiles % cus, kt = d.K / S::BKT;
+    const size_t slot = size_t(S::BM) * S::BN * (CPLX ? 2 : 1) * sizeof(T);
+    const int64_t slots = int64_t(d.tail_ws_bytes / slot);
+    int R = int(std::min<int64_t>(std::min<int64_t>(cus, slots) / std::max<int64_t>(tail, 1),
+                                  std::min<int64_t>(8, kt / 8)));
+    if (full >= 4 && tail > 0 && tail * 4 <= cus && R >= 2) {
+      const int64_t kc = (kt + R - 1) / R;
+      R = int((kt + kc - 1) / kc);         // every K range non-empty
+      const int base = int(full * cus);
+      hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN,
+                                      S::PADB>),
+                         dim3(unsigned(base)), block, 0, s, p);
+      TC_TRY_HIP(hipGetLastError());
+      hipLaunchKernelGGL((gemm_tail_kernel<T, CPLX, AK, BK, S::BM, S::BN, S::BKT, S::WM, S::WN,
+                                           S::PADB>),
+                         dim3(unsigned(tail * R)), block, 0, s, p, base, R, int(kc), d.tail_ws,
+                         slot);
+      TC_TRY_HIP(hipGetLastError());
+      hipLaunchKernelGGL((gemm_tail_finish_kernel<T, CPLX, AK, BK, S::BM, S::BN, S::BKT, S::WM,
+                                                  S::WN, S::PADB>),
+                         dim3(unsigned(tail)), block, 0, s, p, base, R,
+                         static_cast<const void*>(d.tail_ws), slot);
+      TC_TRY_HIP(hipGetLastError());
+      return TC_OK;
+    }
+  }
   if (exact)
     hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN, S::PADB>),
                        grid, block, 0, s, p);
