@@ -45,7 +45,7 @@ def kernel_source_hash(path):
 
 
 def traffic_entry(kernel, workload, src):
-    """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json),
+    """HBM bytes per product measured with rocprofv3 counters (profiles/traffic.json),
     only if recorded for the kernel source as it is now."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
@@ -758,10 +758,12 @@ def main():
     out["expm_s"] = expm_s
 
     # roofline of the dominant kernel (the complex product), from live events:
-    # a launch is one complex N x N x N product, 8 N^3 flop on the method's
-    # count; the launches alternate between the full first product and the
-    # upper tile triangle of the second, so a launch executes flop_exec / 2 on
-    # average, and the split form issues three BF16 products per real product
+    # a "launch" here is one complex N x N x N product, 8 N^3 flop on the
+    # method's count (for the upper tile triangle of the second product: its
+    # main launch and the split-K pair of its last round, timed together); the
+    # products alternate between the full first product and that triangle, so
+    # a product executes flop_exec / 2 on average, and the split form issues
+    # three BF16 products per real product
     kern_ms = hs["product_kernel_ms"]
     per_launch_alg = 8.0 * float(N) ** 3
     per_launch_exec = flop_exec / 2.0
