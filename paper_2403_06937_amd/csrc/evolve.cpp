@@ -33,8 +33,8 @@ struct InstPlan {
   ReadoutItem* ritem = nullptr;
   int* counter = nullptr;
   SplitPlanes planes;           // split-BF16 operand planes
-  // FP64 / FP32: partial sums of the Hermitian product's last round (split
-  // over K), for N whose tile triangle spans at least 4 rounds of 256 CUs
+  // FP64 / FP32: partial sums of a product's last round (split over K), for
+  // N of at least 16 tile rows
   void* tail_ws = nullptr; size_t tail_ws_bytes = 0;
   // excitation-sector stepping (opts.sectors): rho and X in the sorted order
   // Each sector's positions are padded to a multiple of the product tile
@@ -159,12 +159,12 @@ void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
 }
 
 // Lays out (or sizes, when ar.base == nullptr) the workspace of one instance.
-// Slots for the partial sums of the Hermitian FP64 / FP32 product's last
-// round: 256 tiles of 128 x 128 complex elements of eb bytes (64 MB in FP64),
-// once the tile triangle spans at least 4 rounds of 256 CUs.
+// Slots for the partial sums of an FP64 / FP32 product's last round split
+// over K: 256 tiles of 128 x 128 complex elements of eb bytes (64 MB in
+// FP64), once N has at least 16 tile rows.
 void take_tail_ws(Arena& ar, int64_t N, size_t eb, InstPlan* p) {
   const int64_t t = (N + 127) / 128;
-  if (t * (t + 1) / 2 < 4 * 256) return;
+  if (t < 16) return;
   p->tail_ws_bytes = size_t(256) * 128 * 128 * eb;
   p->tail_ws = ar.take(p->tail_ws_bytes);
 }
@@ -758,6 +758,7 @@ void step_descs(const InstPlan& p, const tc_evolve_opts& o, GemmDesc& g1, GemmDe
   g1.B = p.rho; g1.ldb = p.ldr; g1.b_kmaj = true;
   g1.C = p.X; g1.ldc = p.ldx;
   if (rot) { g1.Cin = p.rho; g1.ldcin = p.ldr; g1.beta_re = 1.0; }
+  g1.tail_ws = p.tail_ws; g1.tail_ws_bytes = p.tail_ws_bytes;
   g2 = GemmDesc();
   g2.M = g2.N = g2.K = p.N;
   g2.A = p.X; g2.lda = p.ldx; g2.a_kmaj = false;

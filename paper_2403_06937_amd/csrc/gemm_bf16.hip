@@ -732,14 +732,22 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
   split_tile<WGM, WGN, WM, WN, PP>(p, tm, tn, sA, sB);
 }
 
-// The Hermitian product's last round, split over K.  Its 4656 tiles at
-// N = 12288 fill 18 rounds of 256 CUs and leave 48 for a 19th that would hold
-// most CUs idle for a whole tile.  Instead those tiles are cut into S K ranges
-// (one workgroup each, S x 48 <= 256): split_tail_kernel writes each range's
+// A product's last round, split over K.  The Hermitian product's 4656 tiles
+// at N = 12288 fill 18 rounds of 256 CUs and leave 48 for a 19th that would
+// hold most CUs idle for a whole tile (at N = 5120 the full product leaves 64
+// after 6 rounds).  Instead those tiles are cut into S K ranges (one
+// workgroup each, S x tail <= 256): split_tail_kernel writes each range's
 // FP32 accumulators to a slot of acc, and split_tail_finish_kernel adds a
 // tile's S slots in order (deterministic) and runs the usual epilogue, mirror
-// included.  Positions base .. base + tail - 1 of the triangle's order are
+// included.  Positions base .. base + tail - 1 of the launch's tile order are
 // the tiles the main launch (grid base) leaves out.
+__device__ __forceinline__ void launch_tile(const SplitParams& p, int pid, int& tm, int& tn) {
+  if (p.herm)
+    tri_coords(xcd_linear(pid, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  else
+    tile_coords(pid, p.tiles_m, p.tiles_n, tm, tn);
+}
+
 constexpr int TAIL_SLOTS = 256;                        // slots of acc
 constexpr int TILE_ACC = SPLIT_BM * SPLIT_BN * 2;      // floats per slot (128 KB)
 
@@ -748,7 +756,7 @@ split_tail_kernel(const SplitParams p, int base, int S, int kc, float* __restric
   __shared__ SplitLds sA, sB;
   const int i = blockIdx.x / S, r = blockIdx.x % S;
   int tm, tn;
-  tri_coords(xcd_linear(base + i, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  launch_tile(p, base + i, tm, tn);
   const int64_t ktiles = p.Kp / SPLIT_BK;
   const int64_t k0 = int64_t(r) * kc;
   SplitParams q = p;
@@ -764,7 +772,7 @@ split_tail_finish_kernel(const SplitParams p, int base, int S, const float* __re
   constexpr int NT = 512, WM = 4, WN = 2, WGN = 4;
   const int i = blockIdx.x;
   int tm, tn;
-  tri_coords(xcd_linear(base + i, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  launch_tile(p, base + i, tm, tn);
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
@@ -789,8 +797,8 @@ split_tail_finish_kernel(const SplitParams p, int base, int S, const float* __re
   }
   const int64_t m0 = int64_t(tm) * SPLIT_BM, n0 = int64_t(tn) * SPLIT_BN;
   u4* stage = (wave < 4 ? &sA[0][0][0] : &sB[0][0][0]) + (wave & 3) * 1024;
-  split_epilogue_staged(p, acc_re, acc_im, m0 + wm * WM * 16, n0 + wn * WN * 16, tm != tn,
-                        stage);
+  split_epilogue_staged(p, acc_re, acc_im, m0 + wm * WM * 16, n0 + wn * WN * 16,
+                        p.herm && tm != tn, stage);
 }
 
 // Many split products in one launch, one workgroup per tile of the
@@ -937,15 +945,15 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
     return TC_ERR_INVALID_ARGUMENT;
   }
   ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
-  if (herm && tail_acc && split_variant() == 0) {
-    // a last round of at most a quarter of the CUs after at least 4 full
+  if (tail_acc && split_variant() == 0) {
+    // a last round of at most a quarter of the CUs after at least 2 full
     // rounds: its tiles go split over K into up to TAIL_SLOTS workgroups
     int cus = 0;
     TC_RETURN_IF(device_cu_count(&cus));
     const int64_t full = tiles / cus, tail = tiles % cus, kt = Kp / SPLIT_BK;
     int S = int(std::min<int64_t>(std::min<int64_t>(cus, TAIL_SLOTS) / std::max<int64_t>(tail, 1),
                                   std::min<int64_t>(8, kt / 8)));
-    if (full >= 4 && tail > 0 && tail * 4 <= cus && S >= 2) {
+    if (full >= 2 && tail > 0 && tail * 4 <= cus && S >= 2) {
       const int64_t kc = (kt + S - 1) / S;
       S = int((kt + kc - 1) / kc);         // every K range non-empty
       const int base = int(full * cus);
@@ -1042,10 +1050,10 @@ void split_plan(Arena& ar, int64_t N, SplitPlanes* p) {
   p->opB = take_planes(ar, Np, Np);
   p->X = take_planes(ar, Np, Np);
   p->Rt = take_planes(ar, Np, Np);
-  // partial sums for the Hermitian product's last round once its triangle
-  // spans at least 4 rounds of 256 CUs (32 MB)
+  // partial sums for a product's last round split over K, once N has at
+  // least 16 tile rows (32 MB)
   const int64_t t = Np / SPLIT_BM;
-  p->tail_acc = t * (t + 1) / 2 >= 4 * 256
+  p->tail_acc = t >= 16
                     ? static_cast<float*>(ar.take(size_t(TAIL_SLOTS) * TILE_ACC * sizeof(float)))
                     : nullptr;
 }
@@ -1067,7 +1075,7 @@ int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotat
   // X = op rho (+ rho): A = split(op), B = split(rho^T); planes of X row-major
   TC_RETURN_IF(run_split(p.opA, p.Rt, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
                          rotating ? rho : nullptr, ldr, false, rotating ? X : nullptr, ldx,
-                         &p.X, false, false, s));
+                         &p.X, false, false, s, p.tail_acc));
   // rho' = X conj(op) (+ X): A = split(X), B = split(conj(op)^T); FP32 rho and
   // transposed planes of rho for the next step.  rho' is Hermitian, so with
   // herm only its upper tile triangle is multiplied.

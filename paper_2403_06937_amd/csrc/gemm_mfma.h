@@ -32,8 +32,8 @@ struct GemmDesc {
   // only the tiles on and above the tile diagonal are computed, and each
   // off-diagonal tile also stores its conjugate transpose.
   bool herm = false;
-  // optional device buffer for the last round of a Hermitian product split
-  // over K (partial sums of its tiles); nullptr: one pass per tile
+  // optional device buffer for a product's last round split over K (partial
+  // sums of its tiles); nullptr: one pass per tile
   void* tail_ws = nullptr; size_t tail_ws_bytes = 0;
 };
 

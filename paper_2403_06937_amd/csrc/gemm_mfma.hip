@@ -498,13 +498,20 @@ gemm_kernel(const Params p) {
                                                                  lds);
 }
 
-// The Hermitian product's last round split over K, as for the split-BF16
-// product: the main launch runs the triangle's full rounds of one tile per
-// CU, gemm_tail_kernel runs the remaining tiles' S K ranges (kc K tiles each)
-// and stores their accumulators to one slot each of part, and
-// gemm_tail_finish_kernel adds each tile's S slots in order and runs the
-// epilogue (mirror included).  Positions base .. base + tail - 1 of the
-// triangle's order are the tiles the main launch (grid base) leaves out.
+// A product's last round split over K, as for the split-BF16 product: the
+// main launch runs the full rounds of one tile per CU, gemm_tail_kernel runs
+// the remaining tiles' S K ranges (kc K tiles each) and stores their
+// accumulators to one slot each of part, and gemm_tail_finish_kernel adds
+// each tile's S slots in order and runs the epilogue (mirror included for a
+// Hermitian product).  Positions base .. base + tail - 1 of the launch's tile
+// order are the tiles the main launch (grid base) leaves out.
+__device__ __forceinline__ void launch_tile(const Params& p, int pid, int& tm, int& tn) {
+  if (p.herm)
+    tri_coords(xcd_linear(pid, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  else
+    tile_coords(pid, p.tiles_m, p.tiles_n, tm, tn);
+}
+
 template <typename T, bool CPLX, bool AK, bool BK, int BM, int BN, int BKT, int WM, int WN,
           int PADB>
 __global__ void __launch_bounds__(64 * (BM / (16 * WM)) * (BN / (16 * WN)), 1)
@@ -514,7 +521,7 @@ gemm_tail_kernel(const Params p, int base, int S, int kc, void* part, size_t slo
   __shared__ E lds[L::elems];
   const int i = blockIdx.x / S, r = blockIdx.x % S;
   int tm, tn;
-  tri_coords(xcd_linear(base + i, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);
+  launch_tile(p, base + i, tm, tn);
   const int64_t k0 = int64_t(r) * kc * BKT;
   Params q = p;
   q.A = static_cast<const E*>(p.A) + (AK ? k0 * p.lda : k0);
@@ -531,10 +538,9 @@ gemm_tail_finish_kernel(const Params p, int base, int S, const void* part, size_
   typedef TileLds<T, CPLX, BM, BN, BKT, PADB> L;
   __shared__ typename L::E lds[L::elems];
   int tm, tn;
-  tri_coords(xcd_linear(base + int(blockIdx.x), p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm,
-             tn);
+  launch_tile(p, base + int(blockIdx.x), tm, tn);
   gemm_tile<T, CPLX, AK, BK, false, BM, BN, BKT, WM, WN, PADB, TILE_FINISH>(
-      p, tm, tn, tm != tn, lds,
+      p, tm, tn, p.herm && tm != tn, lds,
       const_cast<char*>(static_cast<const char*>(part)) + size_t(blockIdx.x) * S * slot_bytes, S);
 }
 
@@ -699,8 +705,8 @@ int launch_shape(const GemmDesc& d, hipStream_t s) {
   const bool exact = d.M % S::BM == 0 && d.N % S::BN == 0 && d.K % S::BKT == 0 && d.K > 0;
   const dim3 grid{unsigned(tiles), 1u, 1u}, block{unsigned(S::NT), 1u, 1u};
   ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
-  if (p.herm && exact && d.tail_ws) {
-    // a last round of at most a quarter of the CUs after at least 4 full
+  if (exact && d.tail_ws) {
+    // a last round of at most a quarter of the CUs after at least 2 full
     // rounds: its tiles go split over K, one workgroup and slot per range
     const int cus = device_cus();
     const int64_t full = tiles / cus, tail = tiles % cus, kt = d.K / S::BKT;
@@ -708,7 +714,7 @@ int launch_shape(const GemmDesc& d, hipStream_t s) {
     const int64_t slots = int64_t(d.tail_ws_bytes / slot);
     int R = int(std::min<int64_t>(std::min<int64_t>(cus, slots) / std::max<int64_t>(tail, 1),
                                   std::min<int64_t>(8, kt / 8)));
-    if (full >= 4 && tail > 0 && tail * 4 <= cus && R >= 2) {
+    if (full >= 2 && tail > 0 && tail * 4 <= cus && R >= 2) {
       const int64_t kc = (kt + R - 1) / R;
       R = int((kt + kc - 1) / kc);         // every K range non-empty
       const int base = int(full * cus);
