@@ -33,8 +33,8 @@ struct InstPlan {
   ReadoutItem* ritem = nullptr;
   int* counter = nullptr;
   SplitPlanes planes;           // split-BF16 operand planes
-  // FP64 / FP32: partial sums of a product's last round (split over K), for
-  // N of at least 16 tile rows
+  // FP64 / FP32: partial sums of a product's last round split over K
+  // (shared by the instances that are stepped one after another)
   void* tail_ws = nullptr; size_t tail_ws_bytes = 0;
   // excitation-sector stepping (opts.sectors): rho and X in the sorted order
   // Each sector's positions are padded to a multiple of the product tile
@@ -158,15 +158,36 @@ void plan_sectors(const tc_evolve_opts& o, Arena& ar, InstPlan* p) {
   }
 }
 
-// Lays out (or sizes, when ar.base == nullptr) the workspace of one instance.
-// Slots for the partial sums of an FP64 / FP32 product's last round split
-// over K: 256 tiles of 128 x 128 complex elements of eb bytes (64 MB in
-// FP64), once N has at least 16 tile rows.
-void take_tail_ws(Arena& ar, int64_t N, size_t eb, InstPlan* p) {
-  const int64_t t = (N + 127) / 128;
-  if (t < 16) return;
-  p->tail_ws_bytes = size_t(256) * 128 * 128 * eb;
-  p->tail_ws = ar.take(p->tail_ws_bytes);
+// Slots for the partial sums of a dense product's last round split over K:
+// one 128 x 128 tile of complex elements per slot (16 B in FP64, 8 B as FP32
+// in the FP32 and split-BF16 products), 8 per tile of the N x N product and
+// at most 256 (64 MB in FP64); none for a single tile row, whose K is too
+// short to split.
+size_t tail_bytes(const InstPlan& p, const tc_evolve_opts& o) {
+  if (o.sectors) return 0;
+  const int64_t t = (p.N + 127) / 128;
+  if (t < 2) return 0;
+  const size_t eb = o.gemm_mode == TC_GEMM_F64 ? 16 : 8;
+  return size_t(std::min<int64_t>(256, 8 * t * t)) * 128 * 128 * eb;
+}
+
+// One region of slots for instances stepped one after another on one
+// stream (a single instance, or a batch that is not a grouped launch).
+void take_tail(Arena& ar, const tc_evolve_opts& o, InstPlan* plans, int count) {
+  size_t bytes = 0;
+  for (int b = 0; b < count; ++b) bytes = std::max(bytes, tail_bytes(plans[b], o));
+  if (bytes == 0) return;
+  void* ws = ar.take(bytes);
+  for (int b = 0; b < count; ++b) {
+    if (tail_bytes(plans[b], o) == 0) continue;
+    if (o.gemm_mode == TC_GEMM_SPLIT_BF16) {
+      plans[b].planes.tail_acc = static_cast<float*>(ws);
+      plans[b].planes.tail_slots = int(bytes / (size_t(128) * 128 * 8));
+    } else {
+      plans[b].tail_ws = ws;
+      plans[b].tail_ws_bytes = bytes;
+    }
+  }
 }
 
 void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelArgs& m, Arena& ar,
@@ -197,7 +218,6 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
       p->op_own = ar.take(NN * 16); p->op = p->op_own; p->ldop = N;
     }
     p->X = ar.take(NN * 16); p->ldx = N;
-    take_tail_ws(ar, N, 16, p);
   } else {
     // FP32 and split-BF16 keep an FP32 master
     if (o.rho_dtype == TC_C64) {
@@ -208,7 +228,6 @@ void plan_instance(const tc_instance& in, const tc_evolve_opts& o, const ModelAr
     p->op_own = ar.take(NN * 8); p->op = p->op_own; p->ldop = N;
     p->X = ar.take(NN * 8); p->ldx = N;
     if (o.gemm_mode == TC_GEMM_SPLIT_BF16) split_plan(ar, N, &p->planes);
-    else take_tail_ws(ar, N, 8, p);
   }
 }
 
@@ -908,15 +927,17 @@ int tc_evolve_workspace_size(const tc_instance* inst, int32_t count, const tc_ev
   TC_CHECK_ARG(inst != nullptr, "instances is NULL");
   TC_RETURN_IF(validate_opts(o));
   Arena ar(nullptr, 0);
+  std::vector<InstPlan> plans(count);
   for (int b = 0; b < count; ++b) {
     ModelArgs m;
     TC_RETURN_IF(validate_instance(&inst[b], o, &m));
-    InstPlan p;
-    plan_instance(inst[b], *o, m, ar, &p);
+    plan_instance(inst[b], *o, m, ar, &plans[b]);
   }
   if (use_batched(count, *o)) {
     BatchBufs bb;
     plan_batch(ar, count, sector_items(inst, count, *o), &bb);
+  } else {
+    take_tail(ar, *o, plans.data(), count);
   }
   *bytes = ar.used;
   return TC_OK;
@@ -945,6 +966,7 @@ int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o, v
     plan_batch(ar, count, sector_items(inst, count, *o), &bb);
     TC_RETURN_IF(evolve_batched(plans, inst, count, *o, bb, s));
   } else {
+    take_tail(ar, *o, plans.data(), count);
     for (int b = 0; b < count; ++b) TC_RETURN_IF(evolve_one(plans[b], inst[b], *o, s));
   }
   if (o->renorm_every > 0 && o->steps >= o->renorm_every) {
@@ -990,6 +1012,7 @@ int tc_evolve_sector_workspace_size(const tc_instance* inst, int32_t k, const tc
   InstPlan p;
   p.in_sector = k;
   plan_instance(*inst, *o, m, ar, &p);
+  take_tail(ar, *o, &p, 1);
   *bytes = ar.used;
   return TC_OK;
 }
@@ -1011,6 +1034,7 @@ int tc_evolve_sector(const tc_instance* inst, int32_t k, const tc_evolve_opts* o
   InstPlan p;
   p.in_sector = k;
   plan_instance(*inst, *o, m, ar, &p);
+  take_tail(ar, *o, &p, 1);
   TC_RETURN_IF(evolve_one(p, *inst, *o, s));
   if (o->renorm_every > 0 && o->steps >= o->renorm_every) {
     double flag = 0.0;

@@ -36,8 +36,8 @@ struct SplitPlanes {
   Planes4 opB;   // split(conj(op)^T)    rows n: B operand of rho' = X conj(op)
   Planes4 X;     // split(X)             rows m: A operand of the second product
   Planes4 Rt;    // split(rho^T)         rows n: B operand of the first product
-  float* tail_acc = nullptr;   // partial sums of a product's last round (split
-                               // over K); nullptr for small N
+  float* tail_acc = nullptr;   // partial sums of a product's last round split
+  int tail_slots = 0;          // over K: slots of 128 x 128 complex FP32 (or none)
 };
 
 void split_plan(Arena& ar, int64_t N, SplitPlanes* p);

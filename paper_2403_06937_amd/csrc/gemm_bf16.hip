@@ -914,7 +914,7 @@ int device_cu_count(int* cus) {
 int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t Kp, float ar,
               float ai, float br, float bi, const c64* Cin, int64_t ldcin, bool cin_trans, c64* Cf,
               int64_t ldcf, const Planes4* P, bool p_trans, bool herm, hipStream_t s,
-              float* tail_acc = nullptr) {
+              float* tail_acc = nullptr, int tail_slots = 0) {
   SplitParams q;
   q.A = A.base; q.lda = A.ld;
   q.B = B.base; q.ldb = B.ld;
@@ -945,21 +945,25 @@ int run_split(const Planes4& A, const Planes4& B, int64_t M, int64_t N, int64_t 
     return TC_ERR_INVALID_ARGUMENT;
   }
   ProfileScope prof(TC_KERNEL_SPLIT_BF16, s);
-  if (tail_acc && split_variant() == 0) {
-    // a last round of at most a quarter of the CUs after at least 2 full
-    // rounds: its tiles go split over K into up to TAIL_SLOTS workgroups
+  if (tail_acc && tail_slots > 0 && split_variant() == 0) {
+    // a last round that would leave at least half of the CUs idle (the whole
+    // product, when it has that few tiles): its tiles go split over K, one
+    // workgroup and one slot of partial sums per K range of at least 4 K slices
     int cus = 0;
     TC_RETURN_IF(device_cu_count(&cus));
     const int64_t full = tiles / cus, tail = tiles % cus, kt = Kp / SPLIT_BK;
-    int S = int(std::min<int64_t>(std::min<int64_t>(cus, TAIL_SLOTS) / std::max<int64_t>(tail, 1),
-                                  std::min<int64_t>(8, kt / 8)));
-    if (full >= 2 && tail > 0 && tail * 4 <= cus && S >= 2) {
+    const int64_t slots = std::min<int64_t>(tail_slots, TAIL_SLOTS);
+    int S = int(std::min<int64_t>(std::min<int64_t>(cus, slots) / std::max<int64_t>(tail, 1),
+                                  std::min<int64_t>(8, kt / 4)));
+    if (tail > 0 && tail * 2 <= cus && S >= 2) {
       const int64_t kc = (kt + S - 1) / S;
       S = int((kt + kc - 1) / kc);         // every K range non-empty
       const int base = int(full * cus);
-      hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, true>), dim3(unsigned(base)), dim3(512),
-                         0, s, q);
-      TC_TRY_HIP(hipGetLastError());
+      if (base > 0) {
+        hipLaunchKernelGGL((split_gemm_kernel<2, 4, 4, 2, true>), dim3(unsigned(base)),
+                           dim3(512), 0, s, q);
+        TC_TRY_HIP(hipGetLastError());
+      }
       hipLaunchKernelGGL(split_tail_kernel, dim3(unsigned(tail * S)), dim3(512), 0, s, q, base, S,
                          int(kc), tail_acc);
       TC_TRY_HIP(hipGetLastError());
@@ -1050,12 +1054,6 @@ void split_plan(Arena& ar, int64_t N, SplitPlanes* p) {
   p->opB = take_planes(ar, Np, Np);
   p->X = take_planes(ar, Np, Np);
   p->Rt = take_planes(ar, Np, Np);
-  // partial sums for a product's last round split over K, once N has at
-  // least 16 tile rows (32 MB)
-  const int64_t t = Np / SPLIT_BM;
-  p->tail_acc = t >= 16
-                    ? static_cast<float*>(ar.take(size_t(TAIL_SLOTS) * TILE_ACC * sizeof(float)))
-                    : nullptr;
 }
 
 int split_operand(const c64* op, int64_t ld, int64_t N, const SplitPlanes& p, hipStream_t s) {
@@ -1075,13 +1073,13 @@ int step_split(c64* rho, int64_t ldr, c64* X, int64_t ldx, int64_t N, bool rotat
   // X = op rho (+ rho): A = split(op), B = split(rho^T); planes of X row-major
   TC_RETURN_IF(run_split(p.opA, p.Rt, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
                          rotating ? rho : nullptr, ldr, false, rotating ? X : nullptr, ldx,
-                         &p.X, false, false, s, p.tail_acc));
+                         &p.X, false, false, s, p.tail_acc, p.tail_slots));
   // rho' = X conj(op) (+ X): A = split(X), B = split(conj(op)^T); FP32 rho and
   // transposed planes of rho for the next step.  rho' is Hermitian, so with
   // herm only its upper tile triangle is multiplied.
   TC_RETURN_IF(run_split(p.X, p.opB, N, N, p.Np, 1.f, 0.f, rotating ? 1.f : 0.f, 0.f,
                          rotating ? X : nullptr, ldx, false, rho, ldr, &p.Rt, true, herm, s,
-                         p.tail_acc));
+                         p.tail_acc, p.tail_slots));
   return TC_OK;
 }
 

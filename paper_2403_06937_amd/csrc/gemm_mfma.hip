@@ -706,22 +706,25 @@ int launch_shape(const GemmDesc& d, hipStream_t s) {
   const dim3 grid{unsigned(tiles), 1u, 1u}, block{unsigned(S::NT), 1u, 1u};
   ProfileScope prof(sizeof(T) == 8 ? TC_KERNEL_GEMM_F64 : TC_KERNEL_GEMM_F32, s);
   if (exact && d.tail_ws) {
-    // a last round of at most a quarter of the CUs after at least 2 full
-    // rounds: its tiles go split over K, one workgroup and slot per range
+    // a last round that would leave at least half of the CUs idle (the whole
+    // product, when it has that few tiles): its tiles go split over K, one
+    // workgroup and one slot of partial sums per K range of at least 4 K tiles
     const int cus = device_cus();
     const int64_t full = tiles / cus, tail = tiles % cus, kt = d.K / S::BKT;
     const size_t slot = size_t(S::BM) * S::BN * (CPLX ? 2 : 1) * sizeof(T);
     const int64_t slots = int64_t(d.tail_ws_bytes / slot);
     int R = int(std::min<int64_t>(std::min<int64_t>(cus, slots) / std::max<int64_t>(tail, 1),
-                                  std::min<int64_t>(8, kt / 8)));
-    if (full >= 2 && tail > 0 && tail * 4 <= cus && R >= 2) {
+                                  std::min<int64_t>(8, kt / 4)));
+    if (tail > 0 && tail * 2 <= cus && R >= 2) {
       const int64_t kc = (kt + R - 1) / R;
       R = int((kt + kc - 1) / kc);         // every K range non-empty
       const int base = int(full * cus);
-      hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM, S::WN,
-                                      S::PADB>),
-                         dim3(unsigned(base)), block, 0, s, p);
-      TC_TRY_HIP(hipGetLastError());
+      if (base > 0) {
+        hipLaunchKernelGGL((gemm_kernel<T, CPLX, AK, BK, false, S::BM, S::BN, S::BKT, S::WM,
+                                        S::WN, S::PADB>),
+                           dim3(unsigned(base)), block, 0, s, p);
+        TC_TRY_HIP(hipGetLastError());
+      }
       hipLaunchKernelGGL((gemm_tail_kernel<T, CPLX, AK, BK, S::BM, S::BN, S::BKT, S::WM, S::WN,
                                            S::PADB>),
                          dim3(unsigned(tail * R)), block, 0, s, p, base, R, int(kc), d.tail_ws,
