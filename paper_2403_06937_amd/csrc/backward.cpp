@@ -34,6 +34,13 @@ namespace {
 
 constexpr int FRECHET_DEGREE = 18;   // ||B|| <= 1/2: first omitted term < 2e-23 relative
 
+// Slots for the partial sums of a product's last round split over K (FP64
+// tiles of 128 x 128 complex elements; an FP32 product fits twice as many).
+struct TailWs {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
 struct BwdLayout {
   bool f64 = true;          // product precision of the backward sweep
   size_t eb = 16;           // element bytes of the sweep
@@ -48,6 +55,7 @@ struct BwdLayout {
   c128* Bs = nullptr;
   c128 *P0 = nullptr, *P1 = nullptr, *Q0 = nullptr, *Q1 = nullptr;
   double* scratch = nullptr;
+  TailWs tail;
 };
 
 void bwd_layout(Arena& ar, int64_t N, const tc_evolve_opts& o, BwdLayout* L) {
@@ -68,13 +76,20 @@ void bwd_layout(Arena& ar, int64_t N, const tc_evolve_opts& o, BwdLayout* L) {
   L->Q0 = static_cast<c128*>(ar.take(NN * 16));
   L->Q1 = static_cast<c128*>(ar.take(NN * 16));
   L->scratch = static_cast<double*>(ar.take(8 * sizeof(double)));
+  // 8 slots per tile of the N x N product, at most 256, from 2 tile rows on
+  const int64_t t = (N + 127) / 128;
+  if (t >= 2) {
+    L->tail.bytes = size_t(std::min<int64_t>(256, 8 * t * t)) * 128 * 128 * 16;
+    L->tail.p = ar.take(L->tail.bytes);
+  }
 }
 
 // General complex product in the sweep precision: C = alpha op(A) op(B) + beta C.
-int cgemm(bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj, bool conj_a, const void* B,
-          int64_t ldb, bool b_kmaj, bool conj_b, void* C, int64_t ldc, double alpha_re,
-          double beta_re, hipStream_t s) {
+int cgemm(const TailWs& tw, bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj,
+          bool conj_a, const void* B, int64_t ldb, bool b_kmaj, bool conj_b, void* C, int64_t ldc,
+          double alpha_re, double beta_re, hipStream_t s) {
   GemmDesc d;
+  d.tail_ws = tw.p; d.tail_ws_bytes = tw.bytes;
   d.M = d.N = d.K = N;
   d.A = A; d.lda = lda; d.a_kmaj = a_kmaj; d.conj_a = conj_a;
   d.B = B; d.ldb = ldb; d.b_kmaj = b_kmaj; d.conj_b = conj_b;
@@ -86,10 +101,11 @@ int cgemm(bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj, bool con
 
 // C = op(A) op(B) + Cin in the sweep precision (Cin must not alias C); herm:
 // C is Hermitian, so only its upper tile triangle is multiplied and mirrored.
-int cgemm_in(bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj, bool conj_a,
-             const void* B, int64_t ldb, bool b_kmaj, bool conj_b, void* C, int64_t ldc,
-             const void* Cin, hipStream_t s, bool herm = false) {
+int cgemm_in(const TailWs& tw, bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj,
+             bool conj_a, const void* B, int64_t ldb, bool b_kmaj, bool conj_b, void* C,
+             int64_t ldc, const void* Cin, hipStream_t s, bool herm = false) {
   GemmDesc d;
+  d.tail_ws = tw.p; d.tail_ws_bytes = tw.bytes;
   d.herm = herm;
   d.M = d.N = d.K = N;
   d.A = A; d.lda = lda; d.a_kmaj = a_kmaj; d.conj_a = conj_a;
@@ -100,9 +116,10 @@ int cgemm_in(bool f64, int64_t N, const void* A, int64_t lda, bool a_kmaj, bool 
 }
 
 // FP64 complex product with complex alpha and a real diagonal shift gamma.
-int zgemm64(int64_t N, const c128* A, const c128* B, c128* C, double ar, double beta,
-            const c128* Cin, double gamma, hipStream_t s) {
+int zgemm64(const TailWs& tw, int64_t N, const c128* A, const c128* B, c128* C, double ar,
+            double beta, const c128* Cin, double gamma, hipStream_t s) {
   GemmDesc d;
+  d.tail_ws = tw.p; d.tail_ws_bytes = tw.bytes;
   d.M = d.N = d.K = N;
   d.A = A; d.lda = N; d.a_kmaj = false;
   d.B = B; d.ldb = N; d.b_kmaj = true;
@@ -524,6 +541,8 @@ int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc
     g2.B = L.D; g2.ldb = N; g2.b_kmaj = true; g2.conj_b = true;
     g2.C = dst; g2.ldc = N; g2.Cin = L.X; g2.ldcin = N; g2.beta_re = 1.0;
     g2.herm = true;   // the state after the step is Hermitian
+    g1.tail_ws = g2.tail_ws = L.tail.p;
+    g1.tail_ws_bytes = g2.tail_ws_bytes = L.tail.bytes;
     TC_RETURN_IF(f64 ? gemm_f64(g1, s) : gemm_f32(g1, s));
     return f64 ? gemm_f64(g2, s) : gemm_f32(g2, s);
   };
@@ -575,16 +594,16 @@ int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc
     for (int64_t st = s1; st > s0; --st) {
       const void* rho_prev = state_at(L, N, st - 1 - s0);
       // Y = U~^dag O_s = O_s + D^dag O_s  (op(A) = conj(D)^T)
-      TC_RETURN_IF(cgemm_in(f64, N, L.D, N, true, true, L.O, N, true, false, L.Y, N, L.O, s));
+      TC_RETURN_IF(cgemm_in(L.tail, f64, N, L.D, N, true, true, L.O, N, true, false, L.Y, N, L.O, s));
       // M += rho_{s-1} Y
       if (f64) {
-        TC_RETURN_IF(cgemm(true, N, rho_prev, N, false, false, L.Y, N, true, false, L.M, N, 1.0, 1.0, s));
+        TC_RETURN_IF(cgemm(L.tail, true, N, rho_prev, N, false, false, L.Y, N, true, false, L.M, N, 1.0, 1.0, s));
       } else {
-        TC_RETURN_IF(cgemm(false, N, rho_prev, N, false, false, L.Y, N, true, false, L.T, N, 1.0, 0.0, s));
+        TC_RETURN_IF(cgemm(L.tail, false, N, rho_prev, N, false, false, L.Y, N, true, false, L.T, N, 1.0, 0.0, s));
         TC_RETURN_IF(launch_accumulate_c64(static_cast<const c64*>(L.T), N, L.M, N, N, s));
       }
       // O_{s-1} = Y U~ = Y + Y D, Hermitian (= U~^dag O_s U~)
-      TC_RETURN_IF(cgemm_in(f64, N, L.Y, N, false, false, L.D, N, true, false, L.O, N, L.Y, s,
+      TC_RETURN_IF(cgemm_in(L.tail, f64, N, L.Y, N, false, false, L.D, N, true, false, L.O, N, L.Y, s,
                             true));
     }
   }
@@ -609,16 +628,16 @@ int tc_evolve_backward(const tc_model* m, const double* H, int64_t ldh, const tc
   TC_TRY_HIP(hipMemsetAsync(Q, 0, NN * 16, s));
   for (int k = FRECHET_DEGREE; k >= 1; --k) {
     const double inv = 1.0 / double(k);
-    TC_RETURN_IF(zgemm64(N, L.Bs, Q, Qn, inv, 0.0, nullptr, 0.0, s));     // Qn = B Q / k
-    TC_RETURN_IF(zgemm64(N, L.M, P, Qn, inv, 1.0, Qn, 0.0, s));           // Qn += M P / k
-    TC_RETURN_IF(zgemm64(N, L.Bs, P, Pn, inv, 0.0, nullptr, 1.0, s));     // Pn = I + B P / k
+    TC_RETURN_IF(zgemm64(L.tail, N, L.Bs, Q, Qn, inv, 0.0, nullptr, 0.0, s));     // Qn = B Q / k
+    TC_RETURN_IF(zgemm64(L.tail, N, L.M, P, Qn, inv, 1.0, Qn, 0.0, s));           // Qn += M P / k
+    TC_RETURN_IF(zgemm64(L.tail, N, L.Bs, P, Pn, inv, 0.0, nullptr, 1.0, s));     // Pn = I + B P / k
     std::swap(P, Pn);
     std::swap(Q, Qn);
   }
   for (int k = 0; k < q; ++k) {
-    TC_RETURN_IF(zgemm64(N, P, Q, Qn, 1.0, 0.0, nullptr, 0.0, s));        // Qn = P Q
-    TC_RETURN_IF(zgemm64(N, Q, P, Qn, 1.0, 1.0, Qn, 0.0, s));             // Qn += Q P
-    TC_RETURN_IF(zgemm64(N, P, P, Pn, 1.0, 0.0, nullptr, 0.0, s));        // Pn = P P
+    TC_RETURN_IF(zgemm64(L.tail, N, P, Q, Qn, 1.0, 0.0, nullptr, 0.0, s));        // Qn = P Q
+    TC_RETURN_IF(zgemm64(L.tail, N, Q, P, Qn, 1.0, 1.0, Qn, 0.0, s));             // Qn += Q P
+    TC_RETURN_IF(zgemm64(L.tail, N, P, P, Pn, 1.0, 0.0, nullptr, 0.0, s));        // Pn = P P
     std::swap(P, Pn);
     std::swap(Q, Qn);
   }
