@@ -236,7 +236,11 @@ int tc_evolve_workspace_size(const tc_instance* inst, int32_t count,
  * steps; record 0 is rho(0).  On return rho holds rho(steps) in the lab frame.
  * count > 1 steps uneven instances together (all share o).  ws: device
  * workspace of tc_evolve_workspace_size bytes.  Synchronises the stream only
- * when a renormalisation finds a non-finite trace (then TC_ERR_NONFINITE). */
+ * when a renormalisation finds a non-finite trace (then TC_ERR_NONFINITE).
+ * Results are bitwise reproducible on a given device; a product whose last
+ * round of tiles would leave at least half of the compute units idle has
+ * those tiles' K sums split into ranges that are added in order, and how it
+ * is split depends on the device's compute-unit count. */
 int tc_evolve(const tc_instance* inst, int32_t count, const tc_evolve_opts* o,
               void* ws, size_t ws_bytes, void* stream);
 

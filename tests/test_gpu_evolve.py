@@ -272,6 +272,29 @@ def test_n9_workload_single_precisions(mode):
     assert perr < 1e-5
 
 
+@pytest.mark.parametrize("n,c", [(8, 8), (9, 5)])
+@pytest.mark.parametrize("mode,frame,rdt,tol", [
+    (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 1e-10),
+    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5),
+    (tcm.TC_GEMM_SPLIT_BF16, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5)])
+def test_partial_rounds_split_over_k(n, c, mode, frame, rdt, tol):
+    """N = 2304 (324 tiles of the full product: one round of 256 CUs and 68
+    tiles, which go split over K; 171 of the triangle, one partial round too
+    large to split) and N = 3072 (576 tiles: two rounds and 64; 300 of the
+    triangle: one round and 44), renormalised every 10 steps: every entry and
+    every 5th population record against the oracle."""
+    inst = ti.random_model(n, c, 400 + n, state="haar2")
+    dt, steps = 0.05, 30
+    rho, pop, _ = run_gpu(inst, dt, steps, mode, frame, renorm=10, rho_dtype=rdt)
+    P = oev.SectorPropagator(inst.n, inst.c, inst.g, inst.omega_a)
+    O = excitation_op(inst.n, inst.c)
+    perr = max(abs(pop[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * dt)) ** 2)))
+               for s in range(0, steps + 1, 5))
+    err = max_entry_error_pure(rho, P.psi(inst.psi0, steps * dt))
+    print(f"N={inst.N} mode={mode} max-entry={err:.3e} pop={perr:.3e}", flush=True)
+    assert err < tol and perr < tol
+
+
 def mid_instance(seed=0):
     """C3-shaped but smaller: n=7, c=5 (N=768), 2 photons x Haar product."""
     return ti.random_model(7, 5, 100 + seed, state="haar2")
