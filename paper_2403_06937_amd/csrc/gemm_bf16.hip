@@ -735,12 +735,13 @@ __global__ void __launch_bounds__(64 * WGM * WGN, 1) split_gemm_kernel(const Spl
 // A product's last round, split over K.  The Hermitian product's 4656 tiles
 // at N = 12288 fill 18 rounds of 256 CUs and leave 48 for a 19th that would
 // hold most CUs idle for a whole tile (at N = 5120 the full product leaves 64
-// after 6 rounds).  Instead those tiles are cut into S K ranges (one
-// workgroup each, S x tail <= 256): split_tail_kernel writes each range's
-// FP32 accumulators to a slot of acc, and split_tail_finish_kernel adds a
-// tile's S slots in order (deterministic) and runs the usual epilogue, mirror
-// included.  Positions base .. base + tail - 1 of the launch's tile order are
-// the tiles the main launch (grid base) leaves out.
+// after 6 rounds; below N = 2048 a whole product has fewer tiles than half
+// the CUs).  Instead those tiles are cut into S K ranges (one workgroup each,
+// S x tail <= 256): split_tail_kernel writes each range's FP32 accumulators
+// to a slot of acc, and split_tail_finish_kernel adds a tile's S slots in
+// order (deterministic) and runs the usual epilogue, mirror included.
+// Positions base .. base + tail - 1 of the launch's tile order are the tiles
+// the main launch (grid base, none when base is 0) leaves out.
 __device__ __forceinline__ void launch_tile(const SplitParams& p, int pid, int& tm, int& tn) {
   if (p.herm)
     tri_coords(xcd_linear(pid, p.tiles_m * (p.tiles_m + 1) / 2), p.tiles_m, tm, tn);

@@ -499,7 +499,8 @@ gemm_kernel(const Params p) {
 }
 
 // A product's last round split over K, as for the split-BF16 product: the
-// main launch runs the full rounds of one tile per CU, gemm_tail_kernel runs
+// main launch runs the full rounds of one tile per CU (none for a product
+// with fewer tiles than half the CUs), gemm_tail_kernel runs
 // the remaining tiles' S K ranges (kc K tiles each) and stores their
 // accumulators to one slot each of part, and gemm_tail_finish_kernel adds
 // each tile's S slots in order and runs the epilogue (mirror included for a
