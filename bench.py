@@ -12,6 +12,9 @@ and timed on its own.
 The headline value is the split-BF16 form (hi/lo 3-term products on BF16
 MFMA, FP32 accumulation, rotating frame) in steps/s; the FP64 and complex
 FP32 forms are measured on the same workload and reported beside it.
+`roofline.mfma_probe` gives what the product kernels' MFMA instructions
+sustain with no memory traffic (zero and random operand bits), the practical
+ceiling against which `roofline.issued_frac` reads.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
@@ -127,6 +130,27 @@ def bench_n9(tcm, pipeline, ti, steps=100):
             "tflops": 16.0 * inst.N ** 3 / (ms * 1e-3) / 1e12,
             "tflops_executed": fx / (ms * 1e-3) / 1e12,
             "executed_frac_of_peak": fx / (ms * 1e-3) / PEAK_F64}
+
+
+def mfma_probe(tcm):
+    """What the MFMA instructions of the product kernels sustain with no memory
+    traffic: one 512-thread workgroup per CU issuing them back to back on
+    register operands, zero and random bits, as fractions of the datasheet
+    peak.  Random-operand BF16 issue draws enough power to lower the clock, so
+    its fraction is the practical ceiling of the split-BF16 product's
+    issued_frac."""
+    kinds = {"bf16_16x16x32": (tcm.TC_PROBE_BF16_16X16X32, PEAK_BF16, 100000),
+             "bf16_32x32x16": (tcm.TC_PROBE_BF16_32X32X16, PEAK_BF16, 100000),
+             "f64_16x16x4": (tcm.TC_PROBE_F64_16X16X4, PEAK_F64, 10000)}
+    out = {}
+    for name, (kind, peak, iters) in kinds.items():
+        tcm.tc_mfma_probe(kind, True, iters // 10)
+        r = {}
+        for label, rnd in (("zero_operands_frac", False), ("random_operands_frac", True)):
+            ms, fl = tcm.tc_mfma_probe(kind, rnd, iters)
+            r[label] = fl / (ms * 1e-3) / peak
+        out[name] = r
+    return out
 
 
 def bench_jc3(tcm, pipeline, ti):
@@ -780,7 +804,8 @@ def main():
                        "algorithmic_flop_per_launch": per_launch_alg,
                        "executed_flop_per_launch": per_launch_exec,
                        "executed_frac": exec_frac,
-                       "issued_frac": (3.0 if head == "split" else 1.0) * exec_frac}
+                       "issued_frac": (3.0 if head == "split" else 1.0) * exec_frac,
+                       "mfma_probe": mfma_probe(tcm)}
 
     if not args.no_cpu:
         # the CPU leg, the one part of the benchmark that runs the oracle: first

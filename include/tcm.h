@@ -378,6 +378,29 @@ int tc_profile_enable(int32_t enable);
  * kernel time (ms) and the number of launches since tc_profile_enable(1). */
 int tc_profile_read(int32_t kernel, double* total_ms, int64_t* launches);
 
+/* ------------------------------------------------------ MFMA rate probe */
+
+/* A diagnostic for reading the product kernels' rooflines (not a step of the
+ * method; for callers that measure the hardware).  Every wave of one
+ * 512-thread workgroup per compute unit issues `iters` rounds of MFMAs of one
+ * kind back to back on operands held in registers, with no memory traffic:
+ *   TC_PROBE_BF16_16X16X32  v_mfma_f32_16x16x32_bf16, 16 accumulators (the
+ *                           instruction of the split-BF16 products)
+ *   TC_PROBE_BF16_32X32X16  v_mfma_f32_32x32x16_bf16, 4 accumulators
+ *   TC_PROBE_F64_16X16X4    v_mfma_f64_16x16x4_f64, 8 accumulators (the FP64
+ *                           products)
+ * random_operands != 0: operand bits from a fixed integer sequence per thread
+ * (finite values); 0: zero operands.  out: device buffer of out_count floats,
+ * caller-owned, at least 512 x (compute units); it receives each thread's
+ * accumulator sum, which keeps the work from being optimised away.  iters in
+ * 1 .. 1e7.  Returns the elapsed milliseconds (hipEvents on the stream) and
+ * the flops issued (2 per multiply-add); synchronises the stream. */
+#define TC_PROBE_BF16_16X16X32 0
+#define TC_PROBE_BF16_32X32X16 1
+#define TC_PROBE_F64_16X16X4   2
+int tc_mfma_probe(int32_t kind, int32_t random_operands, int32_t iters, float* out,
+                  int64_t out_count, double* ms, double* flop, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

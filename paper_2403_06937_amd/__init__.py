@@ -48,12 +48,15 @@ EXPORTED = [
     "tc_profile_enable", "tc_profile_read", "tc_autotune_workspace_size", "tc_autotune",
     "tc_autotune_query", "tc_sector_dim", "tc_sector_states", "tc_sector_spectral_bounds",
     "tc_build_sector_hamiltonian", "tc_evolve_sector_workspace_size", "tc_evolve_sector",
-    "tc_observables_noalloc_max_dim", "tc_observables_noalloc",
+    "tc_observables_noalloc_max_dim", "tc_observables_noalloc", "tc_mfma_probe",
 ]
 
 TC_KERNEL_GEMM_F64 = 0
 TC_KERNEL_GEMM_F32 = 1
 TC_KERNEL_SPLIT_BF16 = 2
+TC_PROBE_BF16_16X16X32 = 0
+TC_PROBE_BF16_32X32X16 = 1
+TC_PROBE_F64_16X16X4 = 2
 
 
 class TcmUnavailable(RuntimeError):
@@ -142,6 +145,7 @@ def lib():
             "tc_observables_noalloc_max_dim": [P(i64)],
             "tc_observables_noalloc": [P(tc_model), vp, i32, i64, i64, vp, vp, vp, vp, vp, vp,
                                        vp],
+            "tc_mfma_probe": [i32, i32, i32, vp, i64, P(f64), P(f64), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -417,6 +421,18 @@ def tc_profile_read(kernel: int):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().tc_profile_read(kernel, ctypes.byref(ms), ctypes.byref(n)), "tc_profile_read")
     return ms.value, n.value
+
+
+def tc_mfma_probe(kind: int, random_operands: bool, iters: int, device="cuda", stream=None):
+    """(milliseconds, flops) of one MFMA rate probe launch (kind TC_PROBE_*)."""
+    import torch
+    props = torch.cuda.get_device_properties(torch.device(device))
+    out = torch.empty(512 * props.multi_processor_count, dtype=torch.float32, device=device)
+    ms, fl = ctypes.c_double(), ctypes.c_double()
+    _check(lib().tc_mfma_probe(kind, 1 if random_operands else 0, iters, _ptr(out), out.numel(),
+                               ctypes.byref(ms), ctypes.byref(fl), _stream(stream)),
+           "tc_mfma_probe")
+    return ms.value, fl.value
 
 
 def tc_autotune_workspace_size(gemm_mode: int, max_N: int) -> int:

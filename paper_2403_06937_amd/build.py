@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtcm.so")
 
 SOURCES = ["gemm_mfma.hip", "gemm_bf16.hip", "elementwise.hip", "api.cpp", "evolve.cpp",
-           "profile.cpp", "backward.cpp", "autotune.cpp", "sectors.hip", "noalloc.hip", "resident.hip"]
+           "profile.cpp", "backward.cpp", "autotune.cpp", "sectors.hip", "noalloc.hip", "resident.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -269,3 +269,16 @@ def test_noalloc_observables_rejects_before_device_work():
     assert L.tc_observables_noalloc(ctypes.byref(m.struct), 0x1000, tcm.TC_C64, m.N, m.N, None,
                                     None, None, None, None, None,
                                     None) == tcm.TC_ERR_INVALID_ARGUMENT
+
+
+def test_mfma_probe_rejects_before_device_work():
+    """Argument errors of the MFMA rate probe come back before any HIP call."""
+    L = tcm.lib()
+    ms, fl = ctypes.c_double(), ctypes.c_double()
+    assert L.tc_mfma_probe(7, 1, 100, None, 0, ctypes.byref(ms), ctypes.byref(fl),
+                           None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert L.tc_mfma_probe(tcm.TC_PROBE_F64_16X16X4, 1, 0, None, 0, ctypes.byref(ms),
+                           ctypes.byref(fl), None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert L.tc_mfma_probe(tcm.TC_PROBE_F64_16X16X4, 1, 10, None, 0, ctypes.byref(ms),
+                           ctypes.byref(fl), None) == tcm.TC_ERR_INVALID_ARGUMENT
+    assert b"iters" in L.tc_last_error() or b"NULL" in L.tc_last_error()

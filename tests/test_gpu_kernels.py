@@ -240,3 +240,26 @@ def test_eq13_readings_shapes(n, c):
     assert got["photon_state"].shape == (min(n, c) + 1,)
     assert np.max(np.abs(got["photon_state"] - oobs.photon_state_probability(rho, n, c))) < 1e-14
     assert np.max(np.abs(got["dicke"] - oobs.dicke_probability(rho, n, c))) < 1e-14
+
+
+@pytest.mark.parametrize("kind,peak", [(tcm.TC_PROBE_BF16_16X16X32, 2.5e15),
+                                       (tcm.TC_PROBE_BF16_32X32X16, 2.5e15),
+                                       (tcm.TC_PROBE_F64_16X16X4, 78.6e12)])
+def test_mfma_probe_rates(kind, peak):
+    """The MFMA rate probe issues what it reports (2 flops per multiply-add,
+    16 / 8 / 8 MFMAs per wave and round on 8 waves of every compute unit)
+    and runs within the datasheet peak: zero operands near it, random ones
+    not faster than zeros by more than timing noise."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per = {tcm.TC_PROBE_BF16_16X16X32: 16 * 16 * 16 * 32 * 2,
+           tcm.TC_PROBE_BF16_32X32X16: 8 * 32 * 32 * 16 * 2,
+           tcm.TC_PROBE_F64_16X16X4: 8 * 16 * 16 * 4 * 2}[kind]
+    iters = 20000 if kind != tcm.TC_PROBE_F64_16X16X4 else 4000
+    tcm.tc_mfma_probe(kind, True, 1000)
+    ms_z, fl_z = tcm.tc_mfma_probe(kind, False, iters)
+    ms_r, fl_r = tcm.tc_mfma_probe(kind, True, iters)
+    assert fl_z == fl_r == float(per) * iters * cus * 8
+    fz, fr = fl_z / (ms_z * 1e-3) / peak, fl_r / (ms_r * 1e-3) / peak
+    print(f"probe kind {kind}: zero operands {fz:.3f} of peak, random {fr:.3f}", flush=True)
+    assert 0.5 < fz < 1.05 and 0.3 < fr < 1.05
+    assert fr < fz * 1.05
