@@ -513,9 +513,12 @@ __global__ void readout_kernel(ModelArgs m, const E* __restrict__ rho, int64_t l
   readout_body(m.n, m.c, rho, ld, map, pop, pdist, pstate, sh);
 }
 
+// advance (a launch of one item only): the kernel also moves the record
+// index on, after the block's last barrier, by which point every thread has
+// read it; a captured step then needs no separate counter launch.
 template <typename E>
 __global__ void grouped_readout_kernel(const ReadoutItem* __restrict__ items,
-                                       const int* __restrict__ counter) {
+                                       int* __restrict__ counter, int advance) {
   __shared__ double sh[TPB / 64];
   const ReadoutItem it = items[blockIdx.x];
   const int64_t r = *counter;
@@ -523,6 +526,7 @@ __global__ void grouped_readout_kernel(const ReadoutItem* __restrict__ items,
   readout_body(it.n, it.c, static_cast<const E*>(it.rho), it.ld, it.map,
                it.pop ? it.pop + r : nullptr, it.pdist ? it.pdist + r * (it.c + 1) : nullptr,
                it.pstate ? it.pstate + r * ns : nullptr, sh);
+  if (advance && threadIdx.x == 0) *counter = int(r) + 1;
 }
 
 __global__ void advance_counter_kernel(int* counter) {
@@ -1123,14 +1127,18 @@ int launch_split_bf16(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
 }
 
 int launch_grouped_readout(const ReadoutItem* items_dev, int count, bool c128_storage,
-                           const int* counter, hipStream_t s) {
+                           int* counter, hipStream_t s, bool advance) {
   if (count == 0) return TC_OK;
+  if (advance && count != 1) {
+    set_error("readout: only a single-item launch can advance the record index");
+    return TC_ERR_INVALID_ARGUMENT;
+  }
   if (c128_storage)
     hipLaunchKernelGGL(grouped_readout_kernel<c128>, dim3(unsigned(count)), dim3(TPB), 0, s,
-                       items_dev, counter);
+                       items_dev, counter, advance ? 1 : 0);
   else
     hipLaunchKernelGGL(grouped_readout_kernel<c64>, dim3(unsigned(count)), dim3(TPB), 0, s,
-                       items_dev, counter);
+                       items_dev, counter, advance ? 1 : 0);
   TC_TRY_HIP(hipGetLastError());
   return TC_OK;
 }

@@ -714,8 +714,7 @@ int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipS
     TC_TRY_HIP(hipMemcpyAsync(p.ritem, &ri, sizeof(ri), hipMemcpyHostToDevice, s));
     TC_TRY_HIP(hipMemsetAsync(p.counter, 0, sizeof(int), s));
     TC_TRY_HIP(hipStreamSynchronize(s));   // ri is host memory of this call
-    TC_RETURN_IF(launch_grouped_readout(p.ritem, 1, c128s, p.counter, s));
-    TC_RETURN_IF(launch_advance_counter(p.counter, s));
+    TC_RETURN_IF(launch_grouped_readout(p.ritem, 1, c128s, p.counter, s, true));
   } else if (rec) {
     TC_RETURN_IF(readout(p, o, in.pop_out, in.photon_dist_out, in.photon_state_out, s));
   }
@@ -726,8 +725,7 @@ int evolve_one(InstPlan& p, const tc_instance& in, const tc_evolve_opts& o, hipS
     if (o.renorm_every > 0 && st % o.renorm_every == 0) TC_RETURN_IF(renorm(p, o, q));
     if (rec && st % o.record_every == 0) {
       if (graph) {
-        TC_RETURN_IF(launch_grouped_readout(p.ritem, 1, c128s, p.counter, q));
-        TC_RETURN_IF(launch_advance_counter(p.counter, q));
+        TC_RETURN_IF(launch_grouped_readout(p.ritem, 1, c128s, p.counter, q, true));
       } else {
         const int64_t r = st / o.record_every;
         TC_RETURN_IF(readout(p, o, in.pop_out ? in.pop_out + r : nullptr,

@@ -67,8 +67,9 @@ struct ReadoutItem {
   const int32_t* map;   // NULL, or the position of each basis state in rho (sector order)
   double* pstate;   // may be NULL
 };
+// advance: also move the record index on (count must be 1)
 int launch_grouped_readout(const ReadoutItem* items_dev, int count, bool c128_storage,
-                           const int* counter, hipStream_t s);
+                           int* counter, hipStream_t s, bool advance = false);
 int launch_advance_counter(int* counter, hipStream_t s);
 
 // Hermitise and divide by Re Tr rho, in FP64.  scratch: device double[2]
