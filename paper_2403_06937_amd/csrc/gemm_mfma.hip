@@ -761,7 +761,12 @@ template <typename T, bool CPLX>
 int launch2(const GemmDesc& d, hipStream_t s) {
   typedef Variants<T, CPLX> V;
   if (!d.a_kmaj && d.b_kmaj) {
-    switch (variant_for(DefaultVariant<T, CPLX>::value)) {
+    // a product of at most 64 x 64 outputs fits one 64 x 64 tile, a quarter
+    // of the padded work of a 128 x 128 one (variant 2 in every element type)
+    const int env = variant_for(-1);
+    const int v = env >= 0 ? env
+                           : (d.M <= 64 && d.N <= 64 ? 2 : DefaultVariant<T, CPLX>::value);
+    switch (v) {
       case 1: return launch_shape<T, CPLX, false, true, typename V::V1>(d, s);
       case 2: return launch_shape<T, CPLX, false, true, typename V::V2>(d, s);
       case 3: return launch_shape<T, CPLX, false, true, typename V::V3>(d, s);
