@@ -761,11 +761,15 @@ template <typename T, bool CPLX>
 int launch2(const GemmDesc& d, hipStream_t s) {
   typedef Variants<T, CPLX> V;
   if (!d.a_kmaj && d.b_kmaj) {
-    // a product of at most 64 x 64 outputs fits one 64 x 64 tile, a quarter
-    // of the padded work of a 128 x 128 one (variant 2 in every element type)
+    // A product of at most 16 tiles of 128 x 128 (N <= 512 when square)
+    // takes 64 x 64 tiles (variant 2 in every element type): four times the
+    // workgroups before the K split of its one partial round, so each
+    // workgroup's share of the work is smaller, and a quarter of the padded
+    // work when the product is smaller than one 128 x 128 tile.  (At N = 768
+    // the K-split 128 x 128 tiles give the shorter critical path.)
     const int env = variant_for(-1);
-    const int v = env >= 0 ? env
-                           : (d.M <= 64 && d.N <= 64 ? 2 : DefaultVariant<T, CPLX>::value);
+    const int64_t t128 = ((d.M + 127) / 128) * ((d.N + 127) / 128);
+    const int v = env >= 0 ? env : (t128 <= 16 ? 2 : DefaultVariant<T, CPLX>::value);
     switch (v) {
       case 1: return launch_shape<T, CPLX, false, true, typename V::V1>(d, s);
       case 2: return launch_shape<T, CPLX, false, true, typename V::V2>(d, s);
