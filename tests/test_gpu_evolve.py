@@ -295,6 +295,29 @@ def test_partial_rounds_split_over_k(n, c, mode, frame, rdt, tol):
     assert err < tol and perr < tol
 
 
+@pytest.mark.parametrize("n,c", [(6, 3), (7, 2), (8, 1)])
+@pytest.mark.parametrize("mode,frame,rdt,tol", [
+    (tcm.TC_GEMM_F64, tcm.TC_FRAME_LAB, torch.complex128, 1e-10),
+    (tcm.TC_GEMM_F32, tcm.TC_FRAME_ROTATING, torch.complex64, 1e-5)])
+@pytest.mark.parametrize("full", [False, True])
+def test_small_products_on_64_tiles(n, c, mode, frame, rdt, tol, full):
+    """N = 256, 384, 512: products of at most 16 tiles of 128 x 128, which run
+    on 64 x 64 tiles with their one partial round split over K (triangle or
+    every tile of the second product): every entry and every 5th population
+    record against the oracle after 40 steps, renormalised every 10."""
+    inst = ti.random_model(n, c, 500 + n, state="gaussian")
+    dt, steps = 0.05, 40
+    rho, pop, _ = run_gpu(inst, dt, steps, mode, frame, renorm=10, rho_dtype=rdt, full=full,
+                          no_resident=True)
+    P = oev.SectorPropagator(inst.n, inst.c, inst.g, inst.omega_a)
+    O = excitation_op(inst.n, inst.c)
+    perr = max(abs(pop[s] - float(np.sum(O * np.abs(P.psi(inst.psi0, s * dt)) ** 2)))
+               for s in range(0, steps + 1, 5))
+    err = max_entry_error_pure(rho, P.psi(inst.psi0, steps * dt))
+    print(f"N={inst.N} mode={mode} full={full} max-entry={err:.3e} pop={perr:.3e}", flush=True)
+    assert err < tol and perr < tol
+
+
 def mid_instance(seed=0):
     """C3-shaped but smaller: n=7, c=5 (N=768), 2 photons x Haar product."""
     return ti.random_model(7, 5, 100 + seed, state="haar2")
