@@ -370,16 +370,30 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int tm, int tn, bool 
 
     for (int64_t kt = 0; kt < ktiles; ++kt) {
       const int buf = int(kt & 1);
+      // the first 4-deep slice's fragments are read before the staged tile
+      // goes to the other buffer, so their latency overlaps the stores
+      E a0[WM], b0[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a0[i] = sA[buf][lrow][(wm * WM + i) * 16 + lcol];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b0[j] = sB[buf][lrow][(wn * WN + j) * 16 + lcol];
       store_tiles(buf ^ 1, kt + 1 < klast ? kt + 1 : klast);
       load_tiles(kt + 2 < klast ? kt + 2 : klast);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int k4 = 0; k4 < BKT / 4; ++k4) {
         E a[WM], b[WN];
+        if (k4 == 0) {
 #pragma unroll
-        for (int i = 0; i < WM; ++i) a[i] = sA[buf][k4 * 4 + lrow][(wm * WM + i) * 16 + lcol];
+          for (int i = 0; i < WM; ++i) a[i] = a0[i];
 #pragma unroll
-        for (int j = 0; j < WN; ++j) b[j] = sB[buf][k4 * 4 + lrow][(wn * WN + j) * 16 + lcol];
+          for (int j = 0; j < WN; ++j) b[j] = b0[j];
+        } else {
+#pragma unroll
+          for (int i = 0; i < WM; ++i) a[i] = sA[buf][k4 * 4 + lrow][(wm * WM + i) * 16 + lcol];
+#pragma unroll
+          for (int j = 0; j < WN; ++j) b[j] = sB[buf][k4 * 4 + lrow][(wn * WN + j) * 16 + lcol];
+        }
 #pragma unroll
         for (int i = 0; i < WM; ++i)
 #pragma unroll
